@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""SpKAdd benchmark on one MI355X.
+
+One step is the whole hot path of the method on one batch of synthetic inputs:
+spkadd_plan (upper bounds, bins, windows), spkadd_symbolic (per-column output
+counts and colptr(B)), and spkadd_numeric (hash accumulation, in-LDS sort,
+write-out).  Inputs are resident in HBM and outputs are preallocated before the
+timed region.  The default workload is k=32 Erdos-Renyi CSC matrices,
+65,536 x 65,536, Poisson(16) rows per column, fp32.
+
+Prints one JSON line: input nnz/s over the timed steps, the roofline entry of the
+dominant kernel (algorithmic bytes per launch / mean launch time, from HIP events
+recorded by the library on the launch stream), and the CPU oracle timed on the
+host on the same inputs.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "SpKAdd input nnz/s + % HBM peak; served p50/p99 latency vs plain launches"
+
+WORKLOADS = {
+    "config2": ("k=32 Erdos-Renyi CSC 65536x65536, Poisson(16) rows/column, fp32 U(-1,1)",
+                lambda: workloads.config2("f32")),
+    "config2_f64": ("k=32 Erdos-Renyi CSC 65536x65536, Poisson(16) rows/column, fp64 U(-1,1)",
+                    lambda: workloads.config2("f64")),
+    "config1": ("k=4 Erdos-Renyi CSC 1000x1000, Poisson(8) rows/column, fp32 U(-1,1)",
+                lambda: workloads.config1("f32")),
+    "config3": ("k=64 R-MAT (a=.57,b=c=.19) 2^20x2^20, edge factor 16, fp32 N(0,1)",
+                lambda: workloads.config3("normal")),
+    "config4": ("k=128 tall-skinny 2^24x1024, 4096 uniform rows/column, fp32 U(-1,1)",
+                lambda: workloads.config4("f32")),
+}
+
+WAVE_E = [1, 2, 3, 4, 5, 6, 8, 10, 12, 16]
+
+
+def kernel_of_column(u: np.ndarray, cap: int, wave_max: int = 1024) -> np.ndarray:
+    """Name of the numeric kernel each column goes to under the default options
+    (mirrors the library's binning by u_j)."""
+    names = np.empty(u.shape[0], dtype=object)
+    names[:] = "empty"
+    e = (u + 63) // 64
+    for E in reversed(WAVE_E):
+        names[(u > 0) & (u <= wave_max) & (e <= E)] = f"num_wave_e{E}"
+    names[(u > wave_max) & (u <= min(cap, 2048))] = "num_wg256"
+    names[(u > max(wave_max, min(cap, 2048))) & (u <= cap)] = "num_wg512"
+    names[u > cap] = "num_window"
+    return names
+
+
+def source_sha() -> str:
+    h = hashlib.sha256()
+    for fn in ("hash_kernels.hip", "device.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2112_10223_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
+    or None when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha") != source_sha():
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 3) -> None:
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}))
+
+
+def cpu_baseline(batch, max_cols: int | None = None):
+    import oracle
+    n = batch.n if max_cols is None else min(batch.n, max_cols)
+    cols = None if n == batch.n else np.arange(n, dtype=np.int64)
+    nnz_in = int(sum(int(batch.colptr[i, n]) for i in range(batch.k)))
+    t0 = time.perf_counter()
+    oracle.spkadd(batch, cols=cols)
+    dt = time.perf_counter() - t0
+    return {"value": nnz_in / dt, "unit": "input nnz/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle (concatenate, qsort, reduce in long double; one thread) on columns 0..{n - 1} "
+                      f"of the same inputs ({nnz_in} input nnz), {dt:.2f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-trace", action="store_true", help="time without per-kernel events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the SpKAdd path here is single-GPU.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    if args.copy_calibration:
+        copy_calibration()
+        return 0
+    from paper_2112_10223_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+
+    desc, make = WORKLOADS[args.workload]
+    batch = make()
+    k, m, n = batch.k, batch.m, batch.n
+    f64 = batch.vals[0].dtype == np.float64
+    vbytes = 8 if f64 else 4
+    dev = torch.device("cuda:0")
+    cps = [torch.from_numpy(np.ascontiguousarray(batch.colptr[i])).to(dev) for i in range(k)]
+    ris = [torch.from_numpy(r).to(dev) for r in batch.rowidx]
+    vas = [torch.from_numpy(v).to(dev) for v in batch.vals]
+    dtype = binding.SPKADD_F64 if f64 else binding.SPKADD_F32
+    opts = binding.make_opts(flags=0 if args.no_trace else binding.SPKADD_FLAG_TRACE)
+
+    # output sizes: one untimed call
+    plan = binding.spkadd_plan(m, n, cps, ris, dtype, opts)
+    colptr_c = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    nnz_out = binding.spkadd_symbolic(plan, colptr_c)
+    stats = binding.spkadd_get_stats(plan)
+    plan.free()
+    rowidx_c = torch.empty(max(nnz_out, 1), dtype=torch.int32, device=dev)
+    vals_c = torch.empty(max(nnz_out, 1), dtype=vas[0].dtype, device=dev)
+    nnz_in = batch.nnz_in
+
+    def step():
+        p = binding.spkadd_plan(m, n, cps, ris, dtype, opts)
+        binding.spkadd_symbolic(p, colptr_c)
+        binding.spkadd_numeric(p, vas, rowidx_c, vals_c)
+        return p
+
+    prev = None
+    for _ in range(args.warmup):
+        p = step()
+        if prev is not None:
+            binding.spkadd_trace(prev)
+            prev.free()
+        prev = p
+    torch.cuda.synchronize()
+    traces = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        p = step()
+        if prev is not None:
+            if traces is not None and prev is not None:
+                tr = binding.spkadd_trace(prev)
+                traces.append(tr)
+            prev.free()
+        prev = p
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    traces.append(binding.spkadd_trace(prev))
+    prev.free()
+    traces = traces[1:]  # the first record belongs to the last warm-up step
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    # per-kernel mean launch time over the timed steps
+    per_kernel = {}
+    for tr in traces:
+        for name, ms in tr:
+            per_kernel.setdefault(name, []).append(ms)
+    mean_ms = {kname: float(np.mean(v)) for kname, v in per_kernel.items()}
+    phase_ms = {"plan": 0.0, "symbolic": 0.0, "numeric": 0.0}
+    for kname, ms in mean_ms.items():
+        ph = "numeric" if kname.startswith("num_") else "symbolic" if kname.startswith(("sym_", "scan", "win_colsum")) \
+            else "plan"
+        phase_ms[ph] += ms
+
+    # algorithmic bytes of the numeric kernels, per launch
+    u = np.zeros(n, dtype=np.int64)
+    for i in range(k):
+        u += np.diff(batch.colptr[i]).astype(np.int64)
+    cnt = np.diff(colptr_c.cpu().numpy().astype(np.int64))
+    cap = stats["window_cap"]
+    kern = kernel_of_column(u, cap)
+    roofline = None
+    num_kernels = [kname for kname in mean_ms if kname.startswith("num_")]
+    if num_kernels:
+        dom = max(num_kernels, key=lambda x: mean_ms[x])
+        sel = kern == dom
+        alg_bytes = int(((4 + vbytes) * (u[sel] + cnt[sel]) + 4 * k + 4).sum())
+        achieved = alg_bytes / (mean_ms[dom] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                    "traffic": measured_traffic(dom, args.workload),
+                    "alg_bytes_per_launch": alg_bytes, "mean_launch_ms": round(mean_ms[dom], 5),
+                    "units_per_launch": int(sel.sum())}
+
+    b_alg = (8 + vbytes) * nnz_in + (4 + vbytes) * nnz_out + 12 * k * (n + 1) + 12 * (n + 1)
+    value = nnz_in / (ms_per_step * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "input nnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if f64 else "f32",
+        "data": "synthetic (seeded generator; paper's R-MAT family, no public datasets)",
+        "config": {"workload": f"{args.workload}: {desc}", "k": k, "m": m, "n": n, "nnz_in": nnz_in,
+                   "nnz_out": nnz_out, "parallelism": "single GPU"},
+        "hbm_gbps_alg_step": round(b_alg / (ms_per_step * 1e-3) / 1e9, 1),
+        "hbm_frac_alg_step": round(b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "phase_ms": {kk: round(v, 4) for kk, v in phase_ms.items()},
+        "kernel_ms": {kk: round(v, 5) for kk, v in sorted(mean_ms.items())},
+        "bins": {kk: stats[kk] for kk in ("n_wave_cols", "n_wg_cols", "n_window_cols", "n_windows")},
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(batch)
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

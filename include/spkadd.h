@@ -1,0 +1,180 @@
+/*
+ * spkadd.h -- C ABI of the MI355X (gfx950) SpKAdd library.
+ *
+ * SpKAdd (Section II-A of "Parallel Algorithms for Adding a Collection of Sparse
+ * Matrices") computes B = A_1 + A_2 + ... + A_k for k sparse matrices that all have
+ * the same shape m x n.  This library implements the paper's hash and sliding-hash
+ * k-way method (Algorithms 5-8) as GPU kernels:
+ *   plan     -- upper bound u_j = sum_i nnz(A_i(:,j)) per column, binning of the
+ *               columns, and the row windows used for columns too large for one
+ *               on-chip table (the sliding hash, Section III-B);
+ *   symbolic -- nnz(B(:,j)) per column with a key-only hash table (Algorithm 6,
+ *               Section II-D), then an exclusive scan that gives colptr(B);
+ *   numeric  -- per-column hash accumulation (Algorithm 5), then an in-LDS sort of
+ *               each output column and a coalesced write of rows and values.
+ *
+ * Formats (Section II-A, CSC storage).  Every matrix is CSC with
+ *   colptr : int32[n+1], colptr[0] = 0, non-decreasing;
+ *   rowidx : int32[nnz], rows in [0, m), strictly ascending within each column;
+ *   values : float[nnz] (SPKADD_F32) or double[nnz] (SPKADD_F64).
+ * The output B is canonical CSC in the same form.  Its pattern is the union of
+ * the input patterns: explicit zeros and cancellations stay stored, because the
+ * paper's accumulators never test values.  Its rows are ascending.
+ *
+ * Memory.  Every array argument documented as DEVICE is GPU memory on the current
+ * HIP device.  Every "array of pointers" argument is HOST memory that holds k
+ * DEVICE pointers; it is read during the call and not kept.  The caller owns all
+ * inputs and outputs.  The plan owns its workspace, which comes from a
+ * stream-ordered cache inside the library.  Inputs must stay unchanged and alive
+ * from spkadd_plan until spkadd_numeric has finished on the stream.
+ *
+ * Errors.  Every call returns a status and throws no exceptions.  spkadd_last_error()
+ * gives a message for the calling thread.  On an error, outputs are unspecified.
+ * The plan stays usable unless the status is SPKADD_ERR_HIP, which marks it failed.
+ * Argument checks run on the host before any device work.
+ *
+ * Threads.  Different plans may be used from different threads.  One plan must
+ * not be used by two threads at once.
+ */
+#ifndef SPKADD_H
+#define SPKADD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum spkadd_status {
+  SPKADD_OK = 0,
+  SPKADD_ERR_INVALID = 1,     /* bad argument, or malformed input found by validation */
+  SPKADD_ERR_OOM = 2,         /* device or host allocation failed */
+  SPKADD_ERR_HIP = 3,         /* a HIP runtime call failed; the plan is unusable */
+  SPKADD_ERR_STATE = 4,       /* calls out of order (numeric before symbolic) */
+  SPKADD_ERR_OVERFLOW = 5,    /* a count does not fit int32 (u_j, nnz(B)) */
+  SPKADD_ERR_UNSUPPORTED = 6  /* a size this build does not handle (see spkadd_plan) */
+} spkadd_status;
+
+typedef enum spkadd_dtype { SPKADD_F32 = 0, SPKADD_F64 = 1 } spkadd_dtype;
+
+/* opts.flags */
+#define SPKADD_FLAG_VALIDATE 1u /* check every input on the device in spkadd_plan */
+#define SPKADD_FLAG_TRACE 2u    /* time every kernel launch with HIP events */
+
+/* opts.force_bin: test hook that routes columns to one accumulator family */
+#define SPKADD_BIN_AUTO (-1)
+#define SPKADD_BIN_WAVE 0   /* one wavefront per column (columns with u_j <= 1024) */
+#define SPKADD_BIN_WG 1     /* one workgroup per column (columns with u_j <= window_cap) */
+#define SPKADD_BIN_WINDOW 2 /* sliding-hash row windows for every non-empty column */
+
+/* Tuning and test options.  Zero-initialised fields (or opts == NULL) mean "auto". */
+typedef struct spkadd_opts {
+  uint32_t flags;        /* SPKADD_FLAG_* */
+  int32_t force_bin;     /* SPKADD_BIN_*; 0 is "wave", so use SPKADD_BIN_AUTO (-1) for auto */
+  int32_t window_cap;    /* max input entries per row window and per workgroup column;
+                            0 = auto.  Small values force the sliding hash on small inputs. */
+  int32_t hash_mode;     /* 0 = multiplicative hash; 1 = degenerate hash (every row starts
+                            probing at slot 0), a test hook for long probe chains */
+  int32_t wave_max;      /* largest u_j handled one wavefront per column (64..1024); 0 = auto */
+  float load_factor_sym; /* max (input entries / table slots) of symbolic tables; 0 = auto */
+  float load_factor_num; /* max (output entries / table slots) of numeric tables, <= 0.5; 0 = auto */
+  float window_fill;     /* target fill of a row window relative to window_cap; 0 = auto */
+  int32_t reserved[4];
+} spkadd_opts;
+
+typedef struct spkadd_plan_s* spkadd_plan_t;
+
+/* Writes the defaults into *opts (force_bin = SPKADD_BIN_AUTO, everything else auto). */
+void spkadd_opts_default(spkadd_opts* opts);
+
+/*
+ * spkadd_plan -- set up B = A_1 + ... + A_k (Section II-A) and run the planning step:
+ * the per-column upper bounds u_j = sum_i nnz(A_i(:,j)), the binning of the columns
+ * (the load balance of Section III-A), and the row windows of the columns that take
+ * the sliding hash (Section III-B).
+ *   out    : receives the plan (HOST pointer).
+ *   m, n   : rows and columns of every matrix, 0 <= m, n <= INT32_MAX - 1.
+ *   k      : number of inputs, k >= 1.
+ *   colptr : HOST array of k DEVICE pointers, each int32[n+1].
+ *   rowidx : HOST array of k DEVICE pointers, each int32[colptr_i[n]].
+ *   dtype  : value type of the later spkadd_numeric calls.
+ *   opts   : NULL for defaults.
+ *   stream : HIP stream for all device work.  This call waits on the stream once,
+ *            to size the window tables.
+ * Errors: INVALID (null pointers, k < 1, negative sizes, bad option values, or
+ * malformed inputs when SPKADD_FLAG_VALIDATE is set), OVERFLOW (some u_j above
+ * INT32_MAX), OOM, HIP.
+ */
+spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, const int32_t* const* colptr,
+                          const int32_t* const* rowidx, spkadd_dtype dtype, const spkadd_opts* opts,
+                          hipStream_t stream);
+
+/*
+ * spkadd_symbolic -- nnz(B(:,j)) for every column with a key-only hash table per
+ * column or row window (Algorithms 6 and 7, Section II-D), then colptr(B) by an
+ * exclusive scan.
+ *   colptr_c : DEVICE int32[n+1], written with colptr(B).  It must stay valid until
+ *              spkadd_numeric has finished, which reads it.
+ *   nnz_c    : HOST int64 receiving nnz(B).  This call waits on the stream.
+ * Errors: INVALID (null arguments), OVERFLOW (nnz(B) > INT32_MAX), HIP.
+ * It may be called again; every call recomputes the counts.
+ */
+spkadd_status spkadd_symbolic(spkadd_plan_t plan, int32_t* colptr_c, int64_t* nnz_c, hipStream_t stream);
+
+/*
+ * spkadd_numeric -- the values of B (Algorithms 5 and 8): each column or row window
+ * is accumulated in an on-chip hash table.  Its entries are then sorted by row on
+ * chip and written to rowidx_c / values_c at colptr(B).
+ *   values   : HOST array of k DEVICE pointers to the input values (float or double
+ *              as the plan's dtype), aligned with the rowidx arrays given to spkadd_plan.
+ *   rowidx_c : DEVICE int32[nnz(B)].
+ *   values_c : DEVICE float[nnz(B)] or double[nnz(B)].
+ * The call is asynchronous on `stream`.  It may be repeated with new values for
+ * the same patterns.
+ * Errors: STATE (spkadd_symbolic not yet run), INVALID, HIP.
+ */
+spkadd_status spkadd_numeric(spkadd_plan_t plan, const void* const* values, int32_t* rowidx_c, void* values_c,
+                             hipStream_t stream);
+
+/* spkadd_free -- return the plan's workspace to the library cache and release the
+ * plan.  The workspace is reused only after the work queued on the plan's last
+ * stream is done.  NULL is a no-op. */
+spkadd_status spkadd_free(spkadd_plan_t plan);
+
+/* Message describing the last error on the calling thread ("" if none).  It stays
+ * valid until the next call from the same thread. */
+const char* spkadd_last_error(void);
+
+/* Per-plan statistics, filled after spkadd_plan; the nnz_out and pass fields after
+ * spkadd_symbolic. */
+typedef struct spkadd_stats {
+  int64_t nnz_in;        /* sum_i nnz(A_i) */
+  int64_t nnz_out;       /* nnz(B), -1 before spkadd_symbolic */
+  int32_t n_empty_cols;  /* columns with u_j = 0 */
+  int32_t n_wave_cols;   /* columns handled one wavefront each */
+  int32_t n_wg_cols;     /* columns handled one workgroup each */
+  int32_t n_window_cols; /* columns split into row windows (sliding hash) */
+  int32_t n_windows;     /* row windows over all window columns */
+  int32_t window_levels; /* refinement rounds the window split needed */
+  int32_t window_cap;    /* input entries per window target used */
+  int32_t wave_max;      /* wave bin limit used */
+} spkadd_stats;
+spkadd_status spkadd_get_stats(spkadd_plan_t plan, spkadd_stats* out);
+
+/* Kernel timings recorded under SPKADD_FLAG_TRACE by the last plan / symbolic /
+ * numeric calls of this plan.  spkadd_trace_count gives how many launches were
+ * recorded.  spkadd_trace_get copies the kernel name of launch idx (NUL-terminated,
+ * at most name_cap bytes) and its elapsed milliseconds.  It waits for the events to
+ * complete. */
+int32_t spkadd_trace_count(spkadd_plan_t plan);
+spkadd_status spkadd_trace_get(spkadd_plan_t plan, int32_t idx, char* name, int32_t name_cap, float* ms);
+/* Clears the recorded launches of the plan. */
+spkadd_status spkadd_trace_reset(spkadd_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPKADD_H */

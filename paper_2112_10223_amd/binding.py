@@ -1,0 +1,204 @@
+"""ctypes binding of the SpKAdd C ABI (include/spkadd.h).
+
+This layer only marshals arguments: torch device tensors are turned into raw
+pointers and the current torch stream into a hipStream_t.  Every step of the
+computation runs in the HIP kernels of libspkadd.so.  If the library has not been
+built, importing the binding raises; nothing falls back to a CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspkadd.so")
+
+SPKADD_OK, SPKADD_ERR_INVALID, SPKADD_ERR_OOM, SPKADD_ERR_HIP, SPKADD_ERR_STATE, SPKADD_ERR_OVERFLOW, \
+    SPKADD_ERR_UNSUPPORTED = range(7)
+STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OOM", 3: "HIP", 4: "STATE", 5: "OVERFLOW", 6: "UNSUPPORTED"}
+SPKADD_F32, SPKADD_F64 = 0, 1
+SPKADD_FLAG_VALIDATE, SPKADD_FLAG_TRACE = 1, 2
+SPKADD_BIN_AUTO, SPKADD_BIN_WAVE, SPKADD_BIN_WG, SPKADD_BIN_WINDOW = -1, 0, 1, 2
+
+
+class SpkaddError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"SPKADD_ERR_{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("force_bin", ctypes.c_int32), ("window_cap", ctypes.c_int32),
+                ("hash_mode", ctypes.c_int32), ("wave_max", ctypes.c_int32), ("load_factor_sym", ctypes.c_float),
+                ("load_factor_num", ctypes.c_float), ("window_fill", ctypes.c_float),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("nnz_in", ctypes.c_int64), ("nnz_out", ctypes.c_int64), ("n_empty_cols", ctypes.c_int32),
+                ("n_wave_cols", ctypes.c_int32), ("n_wg_cols", ctypes.c_int32), ("n_window_cols", ctypes.c_int32),
+                ("n_windows", ctypes.c_int32), ("window_levels", ctypes.c_int32), ("window_cap", ctypes.c_int32),
+                ("wave_max", ctypes.c_int32)]
+
+
+def declared_functions():
+    """Names of the functions declared in include/*.h (for the export check)."""
+    import re
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    names = []
+    for fn in sorted(os.listdir(inc)):
+        if fn.endswith(".h"):
+            text = open(os.path.join(inc, fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(spkadd_[a-z0-9_]+)\s*\(", text,
+                                flags=re.M)
+    return sorted(set(names))
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.spkadd_opts_default.argtypes = [ctypes.POINTER(Opts)]
+        L.spkadd_opts_default.restype = None
+        L.spkadd_plan.argtypes = [ctypes.POINTER(P), I32, I32, I32, P, P, ctypes.c_int, ctypes.POINTER(Opts), P]
+        L.spkadd_plan.restype = ctypes.c_int
+        L.spkadd_symbolic.argtypes = [P, P, ctypes.POINTER(I64), P]
+        L.spkadd_symbolic.restype = ctypes.c_int
+        L.spkadd_numeric.argtypes = [P, P, P, P, P]
+        L.spkadd_numeric.restype = ctypes.c_int
+        L.spkadd_free.argtypes = [P]
+        L.spkadd_free.restype = ctypes.c_int
+        L.spkadd_last_error.argtypes = []
+        L.spkadd_last_error.restype = ctypes.c_char_p
+        L.spkadd_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
+        L.spkadd_get_stats.restype = ctypes.c_int
+        L.spkadd_trace_count.argtypes = [P]
+        L.spkadd_trace_count.restype = I32
+        L.spkadd_trace_get.argtypes = [P, I32, ctypes.c_char_p, I32, ctypes.POINTER(ctypes.c_float)]
+        L.spkadd_trace_get.restype = ctypes.c_int
+        L.spkadd_trace_reset.argtypes = [P]
+        L.spkadd_trace_reset.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != SPKADD_OK:
+        raise SpkaddError(status, lib().spkadd_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+def _ptr_array(tensors):
+    return (ctypes.c_void_p * len(tensors))(*[t.data_ptr() if t is not None else 0 for t in tensors])
+
+
+def make_opts(**kw) -> Opts:
+    o = Opts()
+    lib().spkadd_opts_default(ctypes.byref(o))
+    for key, val in kw.items():
+        if val is not None:
+            setattr(o, key, val)
+    return o
+
+
+class Plan:
+    """Owning handle of an spkadd_plan_t."""
+
+    def __init__(self, handle, m, n, k, dtype):
+        self.handle = handle
+        self.m, self.n, self.k, self.dtype = m, n, k, dtype
+        self.nnz = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def free(self):
+        if self.handle:
+            lib().spkadd_free(self.handle)
+            self.handle = None
+
+
+def spkadd_plan(m, n, colptrs, rowidxs, dtype=SPKADD_F32, opts: Opts | None = None, stream=None) -> Plan:
+    """colptrs / rowidxs: k int32 device tensors each (torch)."""
+    k = len(colptrs)
+    h = ctypes.c_void_p()
+    cp = _ptr_array(colptrs)
+    ri = _ptr_array(rowidxs)
+    _check(lib().spkadd_plan(ctypes.byref(h), m, n, k, ctypes.cast(cp, ctypes.c_void_p),
+                             ctypes.cast(ri, ctypes.c_void_p), dtype,
+                             ctypes.byref(opts) if opts is not None else None, _stream_ptr(stream)))
+    return Plan(h, m, n, k, dtype)
+
+
+def spkadd_symbolic(plan: Plan, colptr_c, stream=None) -> int:
+    nnz = ctypes.c_int64()
+    _check(lib().spkadd_symbolic(plan.handle, colptr_c.data_ptr(), ctypes.byref(nnz), _stream_ptr(stream)))
+    plan.nnz = int(nnz.value)
+    return plan.nnz
+
+
+def spkadd_numeric(plan: Plan, values, rowidx_c, values_c, stream=None) -> None:
+    va = _ptr_array(values)
+    _check(lib().spkadd_numeric(plan.handle, ctypes.cast(va, ctypes.c_void_p),
+                                rowidx_c.data_ptr() if rowidx_c is not None else None,
+                                values_c.data_ptr() if values_c is not None else None, _stream_ptr(stream)))
+
+
+def spkadd_free(plan: Plan) -> None:
+    plan.free()
+
+
+def spkadd_get_stats(plan: Plan) -> dict:
+    s = Stats()
+    _check(lib().spkadd_get_stats(plan.handle, ctypes.byref(s)))
+    return {name: getattr(s, name) for name, _ in Stats._fields_}
+
+
+def spkadd_trace(plan: Plan, reset: bool = True) -> list:
+    """[(kernel name, ms)] of the launches recorded under SPKADD_FLAG_TRACE."""
+    out = []
+    buf = ctypes.create_string_buffer(64)
+    ms = ctypes.c_float()
+    for i in range(lib().spkadd_trace_count(plan.handle)):
+        _check(lib().spkadd_trace_get(plan.handle, i, buf, 64, ctypes.byref(ms)))
+        out.append((buf.value.decode(), float(ms.value)))
+    if reset:
+        lib().spkadd_trace_reset(plan.handle)
+    return out
+
+
+def spkadd(m, colptrs, rowidxs, values, opts: Opts | None = None, stream=None):
+    """B = A_1 + ... + A_k on the device: plan, symbolic, numeric, free.
+
+    Inputs are k-lists of device tensors (int32 colptr[n+1], int32 rowidx, float32 or
+    float64 values).  Returns (colptr, rowidx, values) of B as device tensors."""
+    import torch
+    n = colptrs[0].shape[0] - 1
+    dtype = SPKADD_F64 if values[0].dtype == torch.float64 else SPKADD_F32
+    dev = colptrs[0].device
+    plan = spkadd_plan(m, n, colptrs, rowidxs, dtype, opts, stream)
+    try:
+        colptr_c = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        nnz = spkadd_symbolic(plan, colptr_c, stream)
+        rowidx_c = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)[:nnz]
+        values_c = torch.empty(max(nnz, 1), dtype=values[0].dtype, device=dev)[:nnz]
+        spkadd_numeric(plan, values, rowidx_c, values_c, stream)
+    finally:
+        plan.free()
+    return colptr_c, rowidx_c, values_c

@@ -1,0 +1,146 @@
+// Internal interface between the host orchestration (spkadd.cpp) and the HIP
+// kernels (plan_kernels.hip, hash_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spk {
+
+// Column bins.  A column's bin is chosen from its upper bound
+// u_j = sum_i nnz(A_i(:,j)) (the per-column load measure of Section III-A).
+//   EMPTY      u_j = 0, nothing to do.
+//   W<E>       one wavefront per column, E entries per lane (u_j <= 64 E).
+//   G1, G2     one workgroup per column (256 / 512 threads).
+//   WIN        the column is cut into row windows (sliding hash, Section III-B);
+//              one workgroup per window.
+enum Bin : int {
+  BIN_EMPTY = 0,
+  BIN_W1, BIN_W2, BIN_W3, BIN_W4, BIN_W5, BIN_W6, BIN_W8, BIN_W10, BIN_W12, BIN_W16,
+  BIN_G1, BIN_G2,
+  BIN_WIN,
+  NBINS
+};
+constexpr int NWAVE_BINS = 10;
+__host__ __device__ constexpr int wave_bin_E(int b) {
+  return b == BIN_W1 ? 1 : b == BIN_W2 ? 2 : b == BIN_W3 ? 3 : b == BIN_W4 ? 4 : b == BIN_W5 ? 5
+       : b == BIN_W6 ? 6 : b == BIN_W8 ? 8 : b == BIN_W10 ? 10 : b == BIN_W12 ? 12 : 16;
+}
+
+// Device error bits (plan->d_err).
+enum : int {
+  ERR_PROBE = 1,      // a hash table ran out of slots (sizing bug)
+  ERR_COUNT = 2,      // numeric entry count differs from the symbolic count
+  ERR_INPUT = 4,      // validation found a malformed input
+  ERR_OVERFLOW = 8,   // a count exceeds int32
+};
+
+// Threads of the workgroup bins.
+constexpr int G1_THREADS = 256;
+constexpr int G2_THREADS = 512;
+constexpr int WAVES_PER_BLOCK = 4;   // wave bins: columns per 256-thread block
+constexpr int PLAN_THREADS = 256;
+
+struct PlanParams {
+  int m, n, k;
+  int wave_max;     // largest u_j of the wave bins
+  int g1_max;       // largest u_j of bin G1
+  int cap_in;       // largest input count of a G2 column or a window
+  int force_bin;    // -1 auto
+  float win_fill;   // target window input count = cap_in * win_fill
+};
+
+// Summary written by the plan kernels and copied to the host once.
+struct PlanSummary {
+  unsigned long long nnz_in;
+  int err;
+  int bin_count[NBINS];
+  int n_windows;
+  int pad;
+};
+
+// Arguments of the per-unit symbolic / numeric kernels.
+struct KArgs {
+  const int* const* cp;   // k device colptr pointers
+  const int* const* ri;   // k device rowidx pointers
+  const void* const* va;  // k device value pointers (numeric)
+  int m, n, k;
+  int ktop;               // largest power of two <= k-1 (0 when k == 1)
+  int hash_mode;
+  int alpha_q;            // table load factor of this phase, in 1/1024
+  int* colcnt;            // symbolic: per-column nnz(B(:,j))
+  const int* colptr_c;    // numeric: colptr(B)
+  int* out_r;             // numeric: rowidx(B)
+  void* out_v;            // numeric: values(B)
+  // windows
+  const int* wcols;       // window column list (column ids)
+  const int* win_c;       // window -> index into wcols
+  const int* brow;        // boundary rows; window w spans boundaries w + win_c[w] and the next
+  const int* bpos;        // boundary positions, k per boundary
+  const int* cntin;       // window input entry counts
+  int* win_cnt;           // symbolic: per-window unique rows
+  const int* win_off;     // numeric: offset of the window inside its output column
+  int* err;
+  const void* dummy;      // 4 KiB: bytes [0,2048) read as zeros by masked-off loads, [2048,4096) write sink
+  int upw;                // wave pipeline: units per wavefront
+  // LDS layout (bytes, per wave for the wave kernels, per block for the workgroup kernels)
+  int ts_max;             // table slots available
+  int off_P, off_adj, off_adjv, off_hist, off_match, slice_bytes;
+};
+
+// ---- plan kernels (plan_kernels.hip) ----
+void launch_bounds(const PlanParams& p, const int* const* d_cp, int* d_u, unsigned char* d_bin, int* d_colcnt,
+                   int* d_hist, PlanSummary* d_sum, hipStream_t s);
+void launch_validate(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, PlanSummary* d_sum,
+                     hipStream_t s);
+void launch_bin_scan(int nblk, int* d_hist, int* d_binoff, PlanSummary* d_sum, hipStream_t s);
+void launch_bin_scatter(const PlanParams& p, const unsigned char* d_bin, const int* d_hist, const int* d_binoff,
+                        int* d_list, hipStream_t s);
+void launch_win_scan(const PlanParams& p, const int* d_list, const int* d_binoff, const int* d_u, int* d_wfirst,
+                     PlanSummary* d_sum, hipStream_t s);
+void launch_check_ptrs(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, PlanSummary* d_sum,
+                       hipStream_t s);
+void launch_win_fill(const PlanParams& p, int n_wcols, const int* d_wfirst, int* d_win_c, int* d_brow, int* d_bcol,
+                     hipStream_t s);
+void launch_win_search(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
+                       const int* d_wfirst, int n_bounds, const int* d_bcol, const int* d_brow, int* d_bpos,
+                       hipStream_t s);
+void launch_win_count(const PlanParams& p, int n_windows, const int* d_win_c, const int* d_brow, const int* d_bpos,
+                      int* d_cntin, int* d_q, PlanSummary* d_sum, hipStream_t s);
+void launch_win_refine_fill(int n_windows, int n_wcols, const int* d_win_c, const int* d_wfirst_old,
+                            const int* d_q, const int* d_newfirst, const int* d_brow_old, int* d_win_c_new,
+                            int* d_brow_new, int* d_bcol_new, int* d_bpar, int* d_bpiece, int* d_wfirst_new,
+                            hipStream_t s);
+void launch_win_refine_search(const PlanParams& p, const int* const* d_ri, int n_bounds_new, const int* d_bcol_new,
+                              const int* d_brow_new, const int* d_bpar, const int* d_bpiece, const int* d_q,
+                              const int* d_bpos_old, int* d_bpos_new, hipStream_t s);
+void launch_win_colsum(int n_wcols, const int* d_wcols, const int* d_wfirst, const int* d_win_cnt, int* d_colcnt,
+                       int* d_win_off, hipStream_t s);
+
+// Exclusive scan of len int32 counts into out[0..len] (out[len] = total).  The total
+// is also stored as int64 in *d_total; totals above INT32_MAX set ERR_OVERFLOW in
+// *d_err and leave out[] unspecified.  d_tmp needs scan_tmp_bytes(len).
+size_t scan_tmp_bytes(int64_t len);
+void launch_scan(const int* d_in, int64_t len, int* d_out, long long* d_total, int* d_err, void* d_tmp,
+                 hipStream_t s);
+
+// ---- hash kernels (hash_kernels.hip) ----
+// LDS bytes needed by one unit of bin b for a phase (per wave for wave bins).
+void lds_layout(int bin, bool numeric, int vbytes, int k, int ts_max, KArgs& a);
+// Table slots needed for up to `entries` entries at load factor alpha_q / 1024.
+int table_slots(int entries, int alpha_q);
+int alpha_to_q(float alpha);
+int bin_threads(int bin);
+int bin_units_per_block(int bin);
+// Launch the symbolic (numeric == false) or numeric kernel of bin b over units
+// list[0..nunits) (windows: list == nullptr and units are window ids).
+hipError_t launch_hash(int bin, bool numeric, bool f64, const KArgs& a, const int* d_list, int nunits,
+                       hipStream_t s);
+const char* hash_kernel_name(int bin, bool numeric);
+// Pipelined wave-bin kernels (wave_kernels.hip): k <= 64 and numeric load factor 1/2.
+bool wave_pipe_ok(int k, int alpha_num_q);
+void lds_layout_pipe(int bin, bool numeric, int vbytes, int ts_max, KArgs& a);
+hipError_t launch_wave_pipe(int bin, bool numeric, bool f64, const KArgs& a, const int* d_list, int nunits,
+                            hipStream_t s);
+int max_lds_bytes();
+
+}  // namespace spk

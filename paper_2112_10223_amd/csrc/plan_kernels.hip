@@ -1,0 +1,500 @@
+// Planning kernels: per-column upper bounds and bins (the load balance of
+// Section III-A), the row windows of the sliding hash (Section III-B), and scans.
+#include <climits>
+
+#include "device.h"
+#include "internal.h"
+
+namespace spk {
+
+__device__ __forceinline__ int classify(long long u, const PlanParams& p) {
+  if (u <= 0) return BIN_EMPTY;
+  if (p.force_bin == 2) return BIN_WIN;
+  if (p.force_bin == 1) {
+    if (u <= p.cap_in) return u <= p.g1_max ? BIN_G1 : BIN_G2;
+    return BIN_WIN;
+  }
+  const int wave_limit = p.force_bin == 0 ? 1024 : p.wave_max;
+  if (u <= wave_limit) {
+    const int e = (int)((u + 63) >> 6);
+    return e <= 1 ? BIN_W1 : e <= 2 ? BIN_W2 : e <= 3 ? BIN_W3 : e <= 4 ? BIN_W4 : e <= 5 ? BIN_W5
+         : e <= 6 ? BIN_W6 : e <= 8 ? BIN_W8 : e <= 10 ? BIN_W10 : e <= 12 ? BIN_W12 : BIN_W16;
+  }
+  if (u <= p.cap_in) return u <= p.g1_max ? BIN_G1 : BIN_G2;
+  return BIN_WIN;
+}
+
+// u_j = sum_i nnz(A_i(:,j)), bin of j, per-block bin histogram, nnz_in.
+__global__ __launch_bounds__(PLAN_THREADS) void k_bounds(PlanParams p, const int* const* __restrict__ cp,
+                                                         int* __restrict__ u, unsigned char* __restrict__ bin,
+                                                         int* __restrict__ colcnt, int* __restrict__ hist,
+                                                         PlanSummary* __restrict__ sum) {
+  __shared__ int wh[PLAN_THREADS / 64][NBINS];
+  __shared__ unsigned long long red[PLAN_THREADS / 64 + 1];
+  const int j = blockIdx.x * PLAN_THREADS + threadIdx.x;
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  long long uj = 0;
+  int b = -1;
+  if (j < p.n) {
+    for (int i = 0; i < p.k; ++i) {
+      const int* c = cp[i];
+      uj += (long long)(c[j + 1] - c[j]);
+    }
+    if (uj > INT_MAX) {
+      atomicOr(&sum->err, ERR_OVERFLOW);
+      uj = INT_MAX;
+    }
+    b = classify(uj, p);
+    u[j] = (int)uj;
+    bin[j] = (unsigned char)b;
+    colcnt[j] = 0;
+  }
+  for (int bb = 0; bb < NBINS; ++bb) {
+    const uint64_t mk = ballot(b == bb);
+    if (lane == 0) wh[w][bb] = __popcll(mk);
+  }
+  const unsigned long long tot = block_sum<PLAN_THREADS>((unsigned long long)uj, red);
+  if (threadIdx.x < NBINS) {
+    int s = 0;
+    for (int v = 0; v < PLAN_THREADS / 64; ++v) s += wh[v][threadIdx.x];
+    hist[blockIdx.x * NBINS + threadIdx.x] = s;
+  }
+  if (threadIdx.x == 0 && tot) atomicAdd(&sum->nnz_in, tot);
+}
+
+// Optional input validation: colptr_i[0] = 0, colptr non-decreasing, rows in [0, m)
+// and strictly ascending within every column.
+__global__ __launch_bounds__(PLAN_THREADS) void k_validate(PlanParams p, const int* const* __restrict__ cp,
+                                                           const int* const* __restrict__ ri,
+                                                           PlanSummary* __restrict__ sum) {
+  const int j = blockIdx.x * PLAN_THREADS + threadIdx.x;
+  if (j >= p.n) return;
+  bool bad = false;
+  for (int i = 0; i < p.k; ++i) {
+    const int* c = cp[i];
+    const int s = c[j], e = c[j + 1];
+    if (j == 0 && s != 0) bad = true;
+    if (e < s || s < 0) {
+      bad = true;
+      continue;
+    }
+    const int* r = ri[i];
+    int prev = -1;
+    for (int q = s; q < e; ++q) {
+      const int row = r[q];
+      if (row <= prev || row >= p.m) bad = true;
+      prev = row;
+    }
+  }
+  if (bad) atomicOr(&sum->err, ERR_INPUT);
+}
+
+// An input with entries must come with a row array.
+__global__ void k_check_ptrs(PlanParams p, const int* const* __restrict__ cp, const int* const* __restrict__ ri,
+                             PlanSummary* __restrict__ sum) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.k) return;
+  if (cp[i][p.n] > 0 && ri[i] == nullptr) atomicOr(&sum->err, ERR_INPUT);
+}
+
+// Exclusive scan, over blocks, of the per-block bin histograms (one bin at a time);
+// bin offsets; bin counts into the summary.  One block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_bin_scan(int nblk, int* __restrict__ hist, int* __restrict__ binoff,
+                                                   PlanSummary* __restrict__ sum) {
+  __shared__ int scratch[1024 / 64 + 1];
+  __shared__ int totals[NBINS];
+  for (int b = 0; b < NBINS; ++b) {
+    int carry = 0;
+    for (int base = 0; base < nblk; base += 1024) {
+      const int t = base + threadIdx.x;
+      const int v = t < nblk ? hist[t * NBINS + b] : 0;
+      int chunk = 0;
+      const int ex = block_excl_scan<1024>(v, scratch, &chunk);
+      if (t < nblk) hist[t * NBINS + b] = carry + ex;
+      carry += chunk;
+    }
+    if (threadIdx.x == 0) totals[b] = carry;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int b = 0; b < NBINS; ++b) {
+      binoff[b] = acc;
+      sum->bin_count[b] = totals[b];
+      acc += totals[b];
+    }
+    binoff[NBINS] = acc;
+  }
+}
+
+// Column ids grouped by bin, in column order inside each bin.
+__global__ __launch_bounds__(PLAN_THREADS) void k_bin_scatter(PlanParams p, const unsigned char* __restrict__ bin,
+                                                              const int* __restrict__ hist,
+                                                              const int* __restrict__ binoff,
+                                                              int* __restrict__ list) {
+  __shared__ int wc[PLAN_THREADS / 64][NBINS];
+  const int j = blockIdx.x * PLAN_THREADS + threadIdx.x;
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  const int b = j < p.n ? (int)bin[j] : -1;
+  int rank = 0;
+  for (int bb = 0; bb < NBINS; ++bb) {
+    const uint64_t mk = ballot(b == bb);
+    if (b == bb) rank = mbcnt(mk);
+    if (lane == 0) wc[w][bb] = __popcll(mk);
+  }
+  __syncthreads();
+  if (b > BIN_EMPTY) {
+    int before = 0;
+    for (int v = 0; v < w; ++v) before += wc[v][b];
+    list[binoff[b] + hist[blockIdx.x * NBINS + b] + before + rank] = j;
+  }
+}
+
+// Initial number of windows of each window column: P = ceil(u / (cap_in * fill)),
+// clamped to [1, m]; exclusive scan into wfirst[0..n_wcols].  One block.
+__global__ __launch_bounds__(1024) void k_win_scan(PlanParams p, const int* __restrict__ list,
+                                                   const int* __restrict__ binoff, const int* __restrict__ u,
+                                                   int* __restrict__ wfirst, PlanSummary* __restrict__ sum) {
+  __shared__ long long scratch[1024 / 64 + 1];
+  const int* wcols = list + binoff[BIN_WIN];
+  const int n_wcols = binoff[BIN_WIN + 1] - binoff[BIN_WIN];
+  const double target = (double)p.cap_in * (double)p.win_fill;
+  long long carry = 0;
+  for (int base = 0; base < n_wcols; base += 1024) {
+    const int c = base + threadIdx.x;
+    long long pc = 0;
+    if (c < n_wcols) {
+      const int uj = u[wcols[c]];
+      pc = (long long)ceil((double)uj / (target > 1.0 ? target : 1.0));
+      if (pc < 1) pc = 1;
+      if (pc > p.m) pc = p.m;
+    }
+    long long chunk = 0;
+    const long long ex = block_excl_scan<1024>(pc, scratch, &chunk);
+    if (c < n_wcols) wfirst[c] = (int)(carry + ex);
+    carry += chunk;
+  }
+  if (threadIdx.x == 0) {
+    if (carry > (long long)(INT_MAX / 2)) {
+      atomicOr(&sum->err, ERR_OVERFLOW);
+      carry = 0;
+    }
+    wfirst[n_wcols] = (int)carry;
+    sum->n_windows = (int)carry;
+  }
+}
+
+// Equal-row-range windows (the paper's split, Algorithms 7-8): window p of column c
+// covers rows [p*m/P, (p+1)*m/P).  Boundary b of column c has index wfirst[c] + c + p.
+__global__ __launch_bounds__(256) void k_win_fill(PlanParams p, int n_wcols, const int* __restrict__ wfirst,
+                                                  int* __restrict__ win_c, int* __restrict__ brow,
+                                                  int* __restrict__ bcol) {
+  const int c = blockIdx.x;
+  if (c >= n_wcols) return;
+  const int w0 = wfirst[c], P = wfirst[c + 1] - w0;
+  for (int q = threadIdx.x; q <= P; q += blockDim.x) {
+    const int b = w0 + c + q;
+    brow[b] = (int)(((long long)q * (long long)p.m) / P);
+    bcol[b] = c;
+    if (q < P) win_c[w0 + q] = c;
+  }
+}
+
+__device__ __forceinline__ int lower_bound_rows(const int* __restrict__ r, int lo, int hi, int row) {
+  while (lo < hi) {
+    const int mid = lo + ((hi - lo) >> 1);
+    if (r[mid] < row) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Position of every boundary row in every input column: bpos[b*k + i].
+__global__ __launch_bounds__(256) void k_win_search(PlanParams p, const int* const* __restrict__ cp,
+                                                    const int* const* __restrict__ ri,
+                                                    const int* __restrict__ wcols, const int* __restrict__ wfirst,
+                                                    int n_bounds, const int* __restrict__ bcol,
+                                                    const int* __restrict__ brow, int* __restrict__ bpos) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (long long)n_bounds * p.k) return;
+  const int b = (int)(t / p.k), i = (int)(t - (long long)b * p.k);
+  const int c = bcol[b];
+  const int j = wcols[c];
+  const int* col = cp[i];
+  const int s = col[j], e = col[j + 1];
+  const int first = wfirst[c] + c, last = wfirst[c + 1] + c;
+  int pos;
+  if (b == first) pos = s;
+  else if (b == last) pos = e;
+  else pos = lower_bound_rows(ri[i], s, e, brow[b]);
+  bpos[t] = pos;
+}
+
+// Input count of every window; windows with more than cap_in entries and more than
+// cap_in rows are cut into q equal row ranges (q[w] = 1 otherwise).
+__global__ __launch_bounds__(256) void k_win_count(PlanParams p, int n_windows, const int* __restrict__ win_c,
+                                                   const int* __restrict__ brow, const int* __restrict__ bpos,
+                                                   int* __restrict__ cntin, int* __restrict__ q,
+                                                   PlanSummary* __restrict__ sum) {
+  const int w = blockIdx.x * 256 + threadIdx.x;
+  if (w >= n_windows) return;
+  const int b = w + win_c[w];
+  const int* lo = bpos + (long long)b * p.k;
+  const int* hi = lo + p.k;
+  long long cnt = 0;
+  for (int i = 0; i < p.k; ++i) cnt += hi[i] - lo[i];
+  const int width = brow[b + 1] - brow[b];
+  int pieces = 1;
+  if (cnt > p.cap_in && width > p.cap_in) {
+    const double target = (double)p.cap_in * (double)p.win_fill;
+    long long qq = (long long)ceil((double)cnt / (target > 1.0 ? target : 1.0));
+    if (qq < 2) qq = 2;
+    if (qq > width) qq = width;
+    pieces = (int)qq;
+    atomicAdd(&sum->pad, 1);  // number of windows still to refine
+  }
+  cntin[w] = cnt > INT_MAX ? INT_MAX : (int)cnt;
+  q[w] = pieces;
+}
+
+// One refinement level: window w becomes q[w] equal row ranges.  newfirst is the
+// exclusive scan of q.
+__global__ __launch_bounds__(256) void k_win_refine_fill(int n_windows, int n_wcols, const int* __restrict__ win_c,
+                                                         const int* __restrict__ wfirst_old,
+                                                         const int* __restrict__ q,
+                                                         const int* __restrict__ newfirst,
+                                                         const int* __restrict__ brow_old,
+                                                         int* __restrict__ win_c_new, int* __restrict__ brow_new,
+                                                         int* __restrict__ bcol_new, int* __restrict__ bpar,
+                                                         int* __restrict__ bpiece, int* __restrict__ wfirst_new) {
+  const int w = blockIdx.x * 256 + threadIdx.x;
+  if (w < n_windows) {
+    const int c = win_c[w];
+    const int pieces = q[w], nw0 = newfirst[w];
+    const int rlo = brow_old[w + c], rhi = brow_old[w + c + 1];
+    for (int t = 0; t < pieces; ++t) {
+      const int nb = nw0 + t + c;
+      brow_new[nb] = rlo + (int)(((long long)t * (long long)(rhi - rlo)) / pieces);
+      bcol_new[nb] = c;
+      bpar[nb] = w;
+      bpiece[nb] = t;
+      win_c_new[nw0 + t] = c;
+    }
+    if (w + 1 == wfirst_old[c + 1]) {  // last window of its column: also the end boundary
+      const int nb = nw0 + pieces + c;
+      brow_new[nb] = rhi;
+      bcol_new[nb] = c;
+      bpar[nb] = w;
+      bpiece[nb] = pieces;
+    }
+  }
+  if (w <= n_wcols) wfirst_new[w] = newfirst[wfirst_old[w]];
+}
+
+__global__ __launch_bounds__(256) void k_win_refine_search(PlanParams p, const int* const* __restrict__ ri,
+                                                           int n_bounds_new, const int* __restrict__ bcol_new,
+                                                           const int* __restrict__ brow_new,
+                                                           const int* __restrict__ bpar,
+                                                           const int* __restrict__ bpiece,
+                                                           const int* __restrict__ q,
+                                                           const int* __restrict__ bpos_old,
+                                                           int* __restrict__ bpos_new) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (long long)n_bounds_new * p.k) return;
+  const int nb = (int)(t / p.k), i = (int)(t - (long long)nb * p.k);
+  const int w = bpar[nb], piece = bpiece[nb], c = bcol_new[nb];
+  const int ob = w + c;  // old lower boundary of the parent window
+  const int lo = bpos_old[(long long)ob * p.k + i], hi = bpos_old[(long long)(ob + 1) * p.k + i];
+  int pos;
+  if (piece == 0) pos = lo;
+  else if (piece == q[w]) pos = hi;
+  else pos = lower_bound_rows(ri[i], lo, hi, brow_new[nb]);
+  bpos_new[t] = pos;
+}
+
+// Per window column: nnz(B(:,j)) = sum of its window counts, and each window's
+// offset inside the column.
+__global__ __launch_bounds__(256) void k_win_colsum(int n_wcols, const int* __restrict__ wcols,
+                                                    const int* __restrict__ wfirst,
+                                                    const int* __restrict__ win_cnt, int* __restrict__ colcnt,
+                                                    int* __restrict__ win_off) {
+  __shared__ int scratch[256 / 64 + 1];
+  const int c = blockIdx.x;
+  if (c >= n_wcols) return;
+  const int w0 = wfirst[c], w1 = wfirst[c + 1];
+  int carry = 0;
+  for (int base = w0; base < w1; base += 256) {
+    const int w = base + threadIdx.x;
+    const int v = w < w1 ? win_cnt[w] : 0;
+    int chunk = 0;
+    const int ex = block_excl_scan<256>(v, scratch, &chunk);
+    if (w < w1) win_off[w] = carry + ex;
+    carry += chunk;
+  }
+  if (threadIdx.x == 0) colcnt[wcols[c]] = carry;
+}
+
+// ---- exclusive scan of int32 counts (three kernels) ----
+constexpr int SCAN_THREADS = 256, SCAN_PER_THREAD = 16, SCAN_TILE = SCAN_THREADS * SCAN_PER_THREAD;
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const int* __restrict__ in, long long len,
+                                                              long long* __restrict__ bsum) {
+  __shared__ long long scratch[SCAN_THREADS / 64 + 1];
+  const long long base = (long long)blockIdx.x * SCAN_TILE;
+  long long s = 0;
+  for (int t = 0; t < SCAN_PER_THREAD; ++t) {
+    const long long x = base + (long long)t * SCAN_THREADS + threadIdx.x;
+    if (x < len) s += in[x];
+  }
+  s = block_sum<SCAN_THREADS>(s, scratch);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(long long* __restrict__ bsum, int nb,
+                                                   long long* __restrict__ total) {
+  __shared__ long long scratch[1024 / 64 + 1];
+  long long carry = 0;
+  for (int base = 0; base < nb; base += 1024) {
+    const int t = base + threadIdx.x;
+    const long long v = t < nb ? bsum[t] : 0;
+    long long chunk = 0;
+    const long long ex = block_excl_scan<1024>(v, scratch, &chunk);
+    if (t < nb) bsum[t] = carry + ex;
+    carry += chunk;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const int* __restrict__ in, long long len,
+                                                             const long long* __restrict__ bsum,
+                                                             const long long* __restrict__ total,
+                                                             int* __restrict__ out, int* __restrict__ err) {
+  __shared__ long long scratch[SCAN_THREADS / 64 + 1];
+  const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_PER_THREAD;
+  int v[SCAN_PER_THREAD];
+  long long s = 0;
+#pragma unroll
+  for (int t = 0; t < SCAN_PER_THREAD; ++t) {
+    const long long x = base + t;
+    v[t] = x < len ? in[x] : 0;
+    s += v[t];
+  }
+  long long run = bsum[blockIdx.x] + block_excl_scan<SCAN_THREADS>(s, scratch);
+  const long long tot = *total;
+  if (tot > INT_MAX) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, ERR_OVERFLOW);
+    return;
+  }
+#pragma unroll
+  for (int t = 0; t < SCAN_PER_THREAD; ++t) {
+    const long long x = base + t;
+    if (x < len) out[x] = (int)run;
+    run += v[t];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[len] = (int)tot;
+}
+
+// ---- host launchers ----
+static inline unsigned grid_for(long long work, int per_block) {
+  return (unsigned)((work + per_block - 1) / per_block);
+}
+
+void launch_bounds(const PlanParams& p, const int* const* d_cp, int* d_u, unsigned char* d_bin, int* d_colcnt,
+                   int* d_hist, PlanSummary* d_sum, hipStream_t s) {
+  if (p.n == 0) return;
+  k_bounds<<<grid_for(p.n, PLAN_THREADS), PLAN_THREADS, 0, s>>>(p, d_cp, d_u, d_bin, d_colcnt, d_hist, d_sum);
+}
+
+void launch_validate(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, PlanSummary* d_sum,
+                     hipStream_t s) {
+  if (p.n == 0) return;
+  k_validate<<<grid_for(p.n, PLAN_THREADS), PLAN_THREADS, 0, s>>>(p, d_cp, d_ri, d_sum);
+}
+
+void launch_bin_scan(int nblk, int* d_hist, int* d_binoff, PlanSummary* d_sum, hipStream_t s) {
+  k_bin_scan<<<1, 1024, 0, s>>>(nblk, d_hist, d_binoff, d_sum);
+}
+
+void launch_bin_scatter(const PlanParams& p, const unsigned char* d_bin, const int* d_hist, const int* d_binoff,
+                        int* d_list, hipStream_t s) {
+  if (p.n == 0) return;
+  k_bin_scatter<<<grid_for(p.n, PLAN_THREADS), PLAN_THREADS, 0, s>>>(p, d_bin, d_hist, d_binoff, d_list);
+}
+
+void launch_win_scan(const PlanParams& p, const int* d_list, const int* d_binoff, const int* d_u, int* d_wfirst,
+                     PlanSummary* d_sum, hipStream_t s) {
+  k_win_scan<<<1, 1024, 0, s>>>(p, d_list, d_binoff, d_u, d_wfirst, d_sum);
+}
+
+void launch_check_ptrs(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, PlanSummary* d_sum,
+                       hipStream_t s) {
+  k_check_ptrs<<<(p.k + 255) / 256, 256, 0, s>>>(p, d_cp, d_ri, d_sum);
+}
+
+void launch_win_fill(const PlanParams& p, int n_wcols, const int* d_wfirst, int* d_win_c, int* d_brow, int* d_bcol,
+                     hipStream_t s) {
+  if (n_wcols == 0) return;
+  k_win_fill<<<n_wcols, 256, 0, s>>>(p, n_wcols, d_wfirst, d_win_c, d_brow, d_bcol);
+}
+
+void launch_win_search(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
+                       const int* d_wfirst, int n_bounds, const int* d_bcol, const int* d_brow, int* d_bpos,
+                       hipStream_t s) {
+  const long long work = (long long)n_bounds * p.k;
+  if (work == 0) return;
+  k_win_search<<<grid_for(work, 256), 256, 0, s>>>(p, d_cp, d_ri, d_wcols, d_wfirst, n_bounds, d_bcol, d_brow,
+                                                   d_bpos);
+}
+
+void launch_win_count(const PlanParams& p, int n_windows, const int* d_win_c, const int* d_brow, const int* d_bpos,
+                      int* d_cntin, int* d_q, PlanSummary* d_sum, hipStream_t s) {
+  if (n_windows == 0) return;
+  k_win_count<<<grid_for(n_windows, 256), 256, 0, s>>>(p, n_windows, d_win_c, d_brow, d_bpos, d_cntin, d_q, d_sum);
+}
+
+void launch_win_refine_fill(int n_windows, int n_wcols, const int* d_win_c, const int* d_wfirst_old,
+                            const int* d_q, const int* d_newfirst, const int* d_brow_old, int* d_win_c_new,
+                            int* d_brow_new, int* d_bcol_new, int* d_bpar, int* d_bpiece, int* d_wfirst_new,
+                            hipStream_t s) {
+  const int work = (n_windows > n_wcols + 1 ? n_windows : n_wcols + 1);
+  k_win_refine_fill<<<grid_for(work, 256), 256, 0, s>>>(n_windows, n_wcols, d_win_c, d_wfirst_old, d_q,
+                                                        d_newfirst, d_brow_old, d_win_c_new, d_brow_new,
+                                                        d_bcol_new, d_bpar, d_bpiece, d_wfirst_new);
+}
+
+void launch_win_refine_search(const PlanParams& p, const int* const* d_ri, int n_bounds_new, const int* d_bcol_new,
+                              const int* d_brow_new, const int* d_bpar, const int* d_bpiece, const int* d_q,
+                              const int* d_bpos_old, int* d_bpos_new, hipStream_t s) {
+  const long long work = (long long)n_bounds_new * p.k;
+  if (work == 0) return;
+  k_win_refine_search<<<grid_for(work, 256), 256, 0, s>>>(p, d_ri, n_bounds_new, d_bcol_new, d_brow_new, d_bpar,
+                                                          d_bpiece, d_q, d_bpos_old, d_bpos_new);
+}
+
+void launch_win_colsum(int n_wcols, const int* d_wcols, const int* d_wfirst, const int* d_win_cnt, int* d_colcnt,
+                       int* d_win_off, hipStream_t s) {
+  if (n_wcols == 0) return;
+  k_win_colsum<<<n_wcols, 256, 0, s>>>(n_wcols, d_wcols, d_wfirst, d_win_cnt, d_colcnt, d_win_off);
+}
+
+size_t scan_tmp_bytes(int64_t len) {
+  const int64_t nb = (len + SCAN_TILE - 1) / SCAN_TILE;
+  return (size_t)(nb + 1) * sizeof(long long);
+}
+
+void launch_scan(const int* d_in, int64_t len, int* d_out, long long* d_total, int* d_err, void* d_tmp,
+                 hipStream_t s) {
+  const int nb = (int)((len + SCAN_TILE - 1) / SCAN_TILE);
+  long long* bsum = (long long*)d_tmp;
+  if (nb == 0) {
+    // empty input: out[0] = 0, total = 0
+    k_scan_top<<<1, 1024, 0, s>>>(bsum, 0, d_total);
+    k_scan_apply<<<1, SCAN_THREADS, 0, s>>>(d_in, 0, bsum, d_total, d_out, d_err);
+    return;
+  }
+  k_scan_reduce<<<nb, SCAN_THREADS, 0, s>>>(d_in, len, bsum);
+  k_scan_top<<<1, 1024, 0, s>>>(bsum, nb, d_total);
+  k_scan_apply<<<nb, SCAN_THREADS, 0, s>>>(d_in, len, bsum, d_total, d_out, d_err);
+}
+
+}  // namespace spk

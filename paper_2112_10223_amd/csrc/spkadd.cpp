@@ -1,0 +1,754 @@
+// Host side of the SpKAdd C ABI: argument checks, the plan object, the workspace
+// cache, and the order of the device passes (plan -> symbolic -> numeric).
+#include "spkadd.h"
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace spk;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+spkadd_status set_error(spkadd_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      return set_error(SPKADD_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                       __FILE__, __LINE__);                                                    \
+    }                                                                                          \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Workspace cache.  Blocks are kept per device and size class (power of two,
+// at least 4 KiB).  A freed block is reused at once on the stream that freed it
+// (stream order makes that safe) and on another stream once an event recorded at
+// free time has completed.
+// ---------------------------------------------------------------------------
+struct CachedBlock {
+  void* ptr;
+  hipStream_t stream;
+  hipEvent_t done;
+};
+
+class WorkspaceCache {
+ public:
+  static WorkspaceCache& get() {
+    static WorkspaceCache* c = new WorkspaceCache();  // never destroyed: outlives static teardown
+    return *c;
+  }
+  static size_t size_class(size_t bytes) {
+    size_t s = 4096;
+    while (s < bytes) s <<= 1;
+    return s;
+  }
+  hipError_t alloc(void** out, size_t bytes, int dev, hipStream_t stream) {
+    const size_t cls = size_class(bytes);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      auto& lst = free_[{dev, cls}];
+      for (size_t t = 0; t < lst.size(); ++t) {
+        CachedBlock b = lst[t];
+        bool ok = b.stream == stream;
+        if (!ok && b.done) ok = hipEventQuery(b.done) == hipSuccess;
+        if (ok) {
+          if (b.done) (void)hipEventDestroy(b.done);
+          lst.erase(lst.begin() + (long)t);
+          *out = b.ptr;
+          return hipSuccess;
+        }
+      }
+    }
+    hipError_t e = hipMalloc(out, cls);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      trim(dev);
+      e = hipMalloc(out, cls);
+    }
+    return e;
+  }
+  void release(void* p, size_t bytes, int dev, hipStream_t stream) {
+    if (!p) return;
+    CachedBlock b{p, stream, nullptr};
+    if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) == hipSuccess) {
+      if (hipEventRecord(b.done, stream) != hipSuccess) {
+        (void)hipEventDestroy(b.done);
+        b.done = nullptr;
+      }
+    } else {
+      b.done = nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu_);
+    free_[{dev, size_class(bytes)}].push_back(b);
+  }
+  // Frees every cached block of the device whose last use has completed.
+  void trim(int dev) {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto& kv : free_) {
+      if (kv.first.first != dev) continue;
+      auto& lst = kv.second;
+      for (size_t t = 0; t < lst.size();) {
+        CachedBlock b = lst[t];
+        if (!b.done || hipEventQuery(b.done) == hipSuccess) {
+          if (b.done) (void)hipEventDestroy(b.done);
+          (void)hipFree(b.ptr);
+          lst.erase(lst.begin() + (long)t);
+        } else {
+          ++t;
+        }
+      }
+    }
+  }
+
+ private:
+  std::mutex mu_;
+  std::map<std::pair<int, size_t>, std::vector<CachedBlock>> free_;
+};
+
+struct TraceRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct spkadd_plan_s {
+  int device = 0;
+  int m = 0, n = 0, k = 0;
+  spkadd_dtype dtype = SPKADD_F32;
+  spkadd_opts opts{};
+  PlanParams pp{};
+  int alpha_sym_q = 0, alpha_num_q = 0;
+  hipStream_t last_stream = nullptr;
+  bool failed = false;
+
+  struct Alloc {
+    void* p;
+    size_t bytes;
+  };
+  std::vector<Alloc> allocs;
+
+  // pointer tables (device)
+  const int** d_cp = nullptr;
+  const int** d_ri = nullptr;
+  const void** d_va = nullptr;
+  // per-column data
+  int* d_u = nullptr;
+  unsigned char* d_bin = nullptr;
+  int* d_colcnt = nullptr;
+  int* d_hist = nullptr;
+  int* d_binoff = nullptr;
+  int* d_list = nullptr;
+  PlanSummary* d_sum = nullptr;
+  PlanSummary h_sum{};
+  int bin_count[NBINS] = {0};
+  int binoff[NBINS + 1] = {0};
+  // windows
+  int n_wcols = 0, n_windows = 0, levels = 0;
+  int* d_wfirst = nullptr;
+  int* d_win_c = nullptr;
+  int* d_brow = nullptr;
+  int* d_bcol = nullptr;
+  int* d_bpos = nullptr;
+  int* d_cntin = nullptr;
+  int* d_win_cnt = nullptr;
+  int* d_win_off = nullptr;
+  int n_cu = 256;
+  void* d_dummy = nullptr;
+  // scan
+  void* d_scan_tmp = nullptr;
+  long long* d_total = nullptr;
+  // table sizes per bin
+  int ts_sym[NBINS] = {0}, ts_num[NBINS] = {0};
+  // symbolic results
+  int32_t* colptr_c = nullptr;
+  int64_t nnz_c = -1;
+  bool sym_done = false;
+  // trace
+  std::vector<TraceRec> trace;
+
+  template <typename T>
+  spkadd_status alloc(T** out, size_t count, hipStream_t s) {
+    const size_t bytes = (count ? count : 1) * sizeof(T);
+    void* p = nullptr;
+    hipError_t e = WorkspaceCache::get().alloc(&p, bytes, device, s);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return set_error(SPKADD_ERR_OOM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    }
+    allocs.push_back({p, bytes});
+    *out = (T*)p;
+    return SPKADD_OK;
+  }
+  void release(void* p, hipStream_t s) {
+    for (size_t t = 0; t < allocs.size(); ++t) {
+      if (allocs[t].p == p) {
+        WorkspaceCache::get().release(p, allocs[t].bytes, device, s);
+        allocs.erase(allocs.begin() + (long)t);
+        return;
+      }
+    }
+  }
+};
+
+namespace {
+
+bool tracing(const spkadd_plan_s* p) { return (p->opts.flags & SPKADD_FLAG_TRACE) != 0; }
+
+struct TraceScope {
+  spkadd_plan_s* p;
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  TraceScope(spkadd_plan_s* p_, const char* n, hipStream_t s_) : p(p_), name(n), s(s_) {
+    if (tracing(p) && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+  }
+  ~TraceScope() {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, s) == hipSuccess) {
+      p->trace.push_back({name, a, b});
+    } else {
+      (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  }
+};
+
+void clear_trace(spkadd_plan_s* p) {
+  for (auto& t : p->trace) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  p->trace.clear();
+}
+
+constexpr int kDefaultCapF32 = 3072;
+constexpr int kDefaultCapF64 = 2048;
+constexpr int kMaxCap = 8192;
+constexpr float kDefaultAlphaSym = 0.5f;
+constexpr float kDefaultAlphaNum = 0.5f;
+constexpr float kDefaultFill = 0.75f;
+
+int ktop_of(int k) {
+  if (k <= 1) return 0;
+  int t = 1;
+  while (t * 2 <= k - 1) t *= 2;
+  return t;
+}
+
+spkadd_status check_lds(spkadd_plan_s* p) {
+  const int vb = p->dtype == SPKADD_F64 ? 8 : 4;
+  const int lmax = max_lds_bytes();
+  for (int b = BIN_W1; b < NBINS; ++b) {
+    if (p->bin_count[b] == 0) continue;
+    for (int numeric = 0; numeric < 2; ++numeric) {
+      KArgs a{};
+      lds_layout(b, numeric != 0, vb, p->k, numeric ? p->ts_num[b] : p->ts_sym[b], a);
+      const long long bytes = (long long)a.slice_bytes * bin_units_per_block(b);
+      if (bytes > lmax)
+        return set_error(SPKADD_ERR_UNSUPPORTED,
+                         "bin %d needs %lld bytes of LDS (k=%d, table %d slots); the device has %d", b, bytes, p->k,
+                         numeric ? p->ts_num[b] : p->ts_sym[b], lmax);
+    }
+  }
+  return SPKADD_OK;
+}
+
+KArgs base_args(const spkadd_plan_s* p) {
+  KArgs a{};
+  a.cp = p->d_cp;
+  a.ri = p->d_ri;
+  a.va = p->d_va;
+  a.m = p->m;
+  a.n = p->n;
+  a.k = p->k;
+  a.ktop = ktop_of(p->k);
+  a.hash_mode = p->opts.hash_mode;
+  a.colcnt = p->d_colcnt;
+  a.wcols = p->d_list + p->binoff[BIN_WIN];
+  a.win_c = p->d_win_c;
+  a.brow = p->d_brow;
+  a.bpos = p->d_bpos;
+  a.cntin = p->d_cntin;
+  a.win_cnt = p->d_win_cnt;
+  a.win_off = p->d_win_off;
+  a.err = &p->d_sum->err;
+  a.dummy = p->d_dummy;
+  a.upw = 1;
+  return a;
+}
+
+spkadd_status sync_summary(spkadd_plan_s* p, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(&p->h_sum, p->d_sum, sizeof(PlanSummary), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return SPKADD_OK;
+}
+
+spkadd_status check_device_err(spkadd_plan_s* p) {
+  const int e = p->h_sum.err;
+  if (e & ERR_INPUT) return set_error(SPKADD_ERR_INVALID, "input validation failed (colptr, row range or order)");
+  if (e & ERR_OVERFLOW) return set_error(SPKADD_ERR_OVERFLOW, "a count exceeds INT32_MAX");
+  if (e & (ERR_PROBE | ERR_COUNT)) {
+    p->failed = true;
+    return set_error(SPKADD_ERR_HIP, "internal error: device flags 0x%x (table sizing)", e);
+  }
+  return SPKADD_OK;
+}
+
+// Builds the row windows of the window columns: equal row ranges first (the
+// paper's split), then windows holding more than cap_in input entries over more
+// than cap_in rows are cut again until none is left.
+spkadd_status build_windows(spkadd_plan_s* p, hipStream_t s) {
+  spkadd_status st;
+  const int nwc = p->n_wcols, k = p->k;
+  int W = p->n_windows;
+  if ((st = p->alloc(&p->d_win_c, W, s))) return st;
+  if ((st = p->alloc(&p->d_brow, (size_t)W + nwc, s))) return st;
+  if ((st = p->alloc(&p->d_bcol, (size_t)W + nwc, s))) return st;
+  if ((st = p->alloc(&p->d_bpos, ((size_t)W + nwc) * k, s))) return st;
+  if ((st = p->alloc(&p->d_cntin, W, s))) return st;
+  int* d_q = nullptr;
+  if ((st = p->alloc(&d_q, W, s))) return st;
+  const int* wcols = p->d_list + p->binoff[BIN_WIN];
+  {
+    TraceScope t(p, "win_fill", s);
+    launch_win_fill(p->pp, nwc, p->d_wfirst, p->d_win_c, p->d_brow, p->d_bcol, s);
+  }
+  {
+    TraceScope t(p, "win_search", s);
+    launch_win_search(p->pp, p->d_cp, p->d_ri, wcols, p->d_wfirst, W + nwc, p->d_bcol, p->d_brow, p->d_bpos, s);
+  }
+  HIP_TRY(hipMemsetAsync(&p->d_sum->pad, 0, sizeof(int), s));
+  {
+    TraceScope t(p, "win_count", s);
+    launch_win_count(p->pp, W, p->d_win_c, p->d_brow, p->d_bpos, p->d_cntin, d_q, p->d_sum, s);
+  }
+  HIP_TRY(hipGetLastError());
+  if ((st = sync_summary(p, s))) return st;
+  p->levels = 0;
+  while (p->h_sum.pad > 0) {
+    if (++p->levels > 64) return set_error(SPKADD_ERR_HIP, "window refinement did not converge");
+    // new window numbering: exclusive scan of the pieces per window
+    int* d_newfirst = nullptr;
+    void* tmp = nullptr;
+    if ((st = p->alloc(&d_newfirst, (size_t)W + 1, s))) return st;
+    if ((st = p->alloc((char**)&tmp, scan_tmp_bytes(W), s))) return st;
+    launch_scan(d_q, W, d_newfirst, p->d_total, &p->d_sum->err, tmp, s);
+    long long total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, p->d_total, sizeof(total), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (total > INT_MAX / 2 || (total + nwc) * (long long)k > (long long)INT_MAX * 64)
+      return set_error(SPKADD_ERR_OVERFLOW, "too many row windows (%lld)", total);
+    const int W2 = (int)total;
+    int *win_c2, *brow2, *bcol2, *bpos2, *bpar, *bpiece, *wfirst2, *cntin2, *q2;
+    if ((st = p->alloc(&win_c2, W2, s))) return st;
+    if ((st = p->alloc(&brow2, (size_t)W2 + nwc, s))) return st;
+    if ((st = p->alloc(&bcol2, (size_t)W2 + nwc, s))) return st;
+    if ((st = p->alloc(&bpos2, ((size_t)W2 + nwc) * k, s))) return st;
+    if ((st = p->alloc(&bpar, (size_t)W2 + nwc, s))) return st;
+    if ((st = p->alloc(&bpiece, (size_t)W2 + nwc, s))) return st;
+    if ((st = p->alloc(&wfirst2, (size_t)nwc + 1, s))) return st;
+    if ((st = p->alloc(&cntin2, W2, s))) return st;
+    if ((st = p->alloc(&q2, W2, s))) return st;
+    {
+      TraceScope t(p, "win_refine_fill", s);
+      launch_win_refine_fill(W, nwc, p->d_win_c, p->d_wfirst, d_q, d_newfirst, p->d_brow, win_c2, brow2, bcol2,
+                             bpar, bpiece, wfirst2, s);
+    }
+    {
+      TraceScope t(p, "win_refine_search", s);
+      launch_win_refine_search(p->pp, p->d_ri, W2 + nwc, bcol2, brow2, bpar, bpiece, d_q, p->d_bpos, bpos2, s);
+    }
+    HIP_TRY(hipMemsetAsync(&p->d_sum->pad, 0, sizeof(int), s));
+    {
+      TraceScope t(p, "win_count", s);
+      launch_win_count(p->pp, W2, win_c2, brow2, bpos2, cntin2, q2, p->d_sum, s);
+    }
+    HIP_TRY(hipGetLastError());
+    if ((st = sync_summary(p, s))) return st;
+    // retire the previous level
+    p->release(p->d_win_c, s);
+    p->release(p->d_brow, s);
+    p->release(p->d_bcol, s);
+    p->release(p->d_bpos, s);
+    p->release(p->d_cntin, s);
+    p->release(d_q, s);
+    p->release(p->d_wfirst, s);
+    p->release(d_newfirst, s);
+    p->release(tmp, s);
+    p->release(bpar, s);
+    p->release(bpiece, s);
+    p->d_win_c = win_c2;
+    p->d_brow = brow2;
+    p->d_bcol = bcol2;
+    p->d_bpos = bpos2;
+    p->d_cntin = cntin2;
+    p->d_wfirst = wfirst2;
+    d_q = q2;
+    W = W2;
+  }
+  p->release(d_q, s);
+  p->n_windows = W;
+  if ((st = p->alloc(&p->d_win_cnt, W, s))) return st;
+  if ((st = p->alloc(&p->d_win_off, W, s))) return st;
+  return SPKADD_OK;
+}
+
+
+bool is_wave(int b) { return b >= BIN_W1 && b <= BIN_W16; }
+
+// Launches the symbolic or numeric kernel of bin b.
+hipError_t launch_bin(spkadd_plan_s* p, int b, bool numeric, KArgs& a, hipStream_t s) {
+  const int cnt = b == BIN_WIN ? p->n_windows : p->bin_count[b];
+  if (cnt == 0) return hipSuccess;
+  const bool f64 = p->dtype == SPKADD_F64;
+  const int vb = f64 ? 8 : 4;
+  const int ts = numeric ? p->ts_num[b] : p->ts_sym[b];
+  const int* list = b == BIN_WIN ? nullptr : p->d_list + p->binoff[b];
+  if (is_wave(b) && wave_pipe_ok(p->k, p->alpha_num_q)) {
+    lds_layout_pipe(b, numeric, vb, ts, a);
+    const int block_lds = a.slice_bytes * WAVES_PER_BLOCK;
+    int bpc = max_lds_bytes() / block_lds;
+    if (bpc > 8) bpc = 8;
+    if (bpc < 1) bpc = 1;
+    const long long resident = (long long)p->n_cu * bpc * WAVES_PER_BLOCK;
+    long long upw = (cnt + resident - 1) / resident;
+    a.upw = (int)(upw < 1 ? 1 : upw > 64 ? 64 : upw);
+    return launch_wave_pipe(b, numeric, f64, a, list, cnt, s);
+  }
+  lds_layout(b, numeric, vb, p->k, ts, a);
+  return launch_hash(b, numeric, f64, a, list, cnt, s);
+}
+
+void release_all(spkadd_plan_s* p) {
+  hipStream_t s = p->last_stream;
+  for (auto& a : p->allocs) WorkspaceCache::get().release(a.p, a.bytes, p->device, s);
+  p->allocs.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+void spkadd_opts_default(spkadd_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->force_bin = SPKADD_BIN_AUTO;
+}
+
+const char* spkadd_last_error(void) { return g_last_error.c_str(); }
+
+spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, const int32_t* const* colptr,
+                          const int32_t* const* rowidx, spkadd_dtype dtype, const spkadd_opts* opts,
+                          hipStream_t stream) {
+  g_last_error.clear();
+  if (!out) return set_error(SPKADD_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (m < 0 || n < 0 || m == INT_MAX || n == INT_MAX)
+    return set_error(SPKADD_ERR_INVALID, "bad shape m=%d n=%d", m, n);
+  if (k < 1) return set_error(SPKADD_ERR_INVALID, "k must be >= 1 (got %d)", k);
+  if (!colptr || !rowidx) return set_error(SPKADD_ERR_INVALID, "colptr / rowidx pointer arrays are NULL");
+  for (int i = 0; i < k; ++i)
+    if (!colptr[i]) return set_error(SPKADD_ERR_INVALID, "colptr[%d] is NULL", i);
+  if (dtype != SPKADD_F32 && dtype != SPKADD_F64) return set_error(SPKADD_ERR_INVALID, "bad dtype %d", (int)dtype);
+  spkadd_opts o;
+  spkadd_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.force_bin < -1 || o.force_bin > 2) return set_error(SPKADD_ERR_INVALID, "bad force_bin %d", o.force_bin);
+  if (o.hash_mode < 0 || o.hash_mode > 1) return set_error(SPKADD_ERR_INVALID, "bad hash_mode %d", o.hash_mode);
+  if (o.wave_max < 0 || o.wave_max > 1024) return set_error(SPKADD_ERR_INVALID, "wave_max must be in [0, 1024]");
+  if (o.window_cap < 0 || o.window_cap > kMaxCap)
+    return set_error(SPKADD_ERR_INVALID, "window_cap must be in [0, %d]", kMaxCap);
+  if (!(o.load_factor_sym >= 0.f && o.load_factor_sym <= 0.9f))
+    return set_error(SPKADD_ERR_INVALID, "load_factor_sym must be in [0, 0.9]");
+  if (!(o.load_factor_num >= 0.f && o.load_factor_num <= 0.5f))
+    return set_error(SPKADD_ERR_INVALID, "load_factor_num must be in [0, 0.5]");
+  if (!(o.window_fill >= 0.f && o.window_fill <= 1.f))
+    return set_error(SPKADD_ERR_INVALID, "window_fill must be in [0, 1]");
+
+  auto* p = new (std::nothrow) spkadd_plan_s();
+  if (!p) return set_error(SPKADD_ERR_OOM, "host allocation failed");
+  auto fail = [&](spkadd_status st) {
+    release_all(p);
+    clear_trace(p);
+    delete p;
+    return st;
+  };
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete p;
+    return set_error(SPKADD_ERR_HIP, "no HIP device");
+  }
+  p->m = m;
+  p->n = n;
+  p->k = k;
+  p->dtype = dtype;
+  p->opts = o;
+  p->last_stream = stream;
+  const int cap = o.window_cap ? o.window_cap : (dtype == SPKADD_F64 ? kDefaultCapF64 : kDefaultCapF32);
+  const float asym = o.load_factor_sym > 0 ? o.load_factor_sym : kDefaultAlphaSym;
+  const float anum = o.load_factor_num > 0 ? o.load_factor_num : kDefaultAlphaNum;
+  p->alpha_sym_q = alpha_to_q(asym);
+  p->alpha_num_q = alpha_to_q(anum);
+  p->pp.m = m;
+  p->pp.n = n;
+  p->pp.k = k;
+  p->pp.wave_max = o.wave_max ? o.wave_max : 1024;
+  p->pp.cap_in = cap;
+  // G1 stages at most 16 numeric table slots per thread; shrink its column limit
+  // until its tables fit (small load factors make tables larger).
+  int g1 = cap < 2048 ? cap : 2048;
+  while (g1 > 64 && table_slots(g1, p->alpha_num_q) > G1_THREADS * 16) g1 -= 64;
+  p->pp.g1_max = g1;
+  p->pp.force_bin = o.force_bin;
+  p->pp.win_fill = o.window_fill > 0 ? o.window_fill : kDefaultFill;
+  for (int b = BIN_W1; b <= BIN_W16; ++b) {
+    p->ts_sym[b] = table_slots(64 * wave_bin_E(b), p->alpha_sym_q);
+    p->ts_num[b] = table_slots(64 * wave_bin_E(b), p->alpha_num_q);
+  }
+  p->ts_sym[BIN_G1] = table_slots(p->pp.g1_max, p->alpha_sym_q);
+  p->ts_num[BIN_G1] = table_slots(p->pp.g1_max, p->alpha_num_q);
+  p->ts_sym[BIN_G2] = p->ts_sym[BIN_WIN] = table_slots(cap, p->alpha_sym_q);
+  p->ts_num[BIN_G2] = p->ts_num[BIN_WIN] = table_slots(cap, p->alpha_num_q);
+  if (p->ts_num[BIN_G1] > G1_THREADS * 16 || p->ts_num[BIN_G2] > G2_THREADS * 32)
+    return fail(set_error(SPKADD_ERR_INVALID, "window_cap / load_factor_num give too large numeric tables"));
+
+  spkadd_status st;
+  const int nblk = (n + PLAN_THREADS - 1) / PLAN_THREADS;
+  void* ptrs = nullptr;
+  if ((st = p->alloc((char**)&ptrs, 3 * (size_t)k * sizeof(void*), stream))) return fail(st);
+  p->d_cp = (const int**)ptrs;
+  p->d_ri = p->d_cp + k;
+  p->d_va = (const void**)(p->d_ri + k);
+  if ((st = p->alloc(&p->d_u, n, stream))) return fail(st);
+  if ((st = p->alloc(&p->d_bin, n, stream))) return fail(st);
+  if ((st = p->alloc(&p->d_colcnt, n, stream))) return fail(st);
+  if ((st = p->alloc(&p->d_hist, (size_t)nblk * NBINS, stream))) return fail(st);
+  if ((st = p->alloc(&p->d_binoff, NBINS + 1, stream))) return fail(st);
+  if ((st = p->alloc(&p->d_list, n, stream))) return fail(st);
+  if ((st = p->alloc(&p->d_sum, 1, stream))) return fail(st);
+  if ((st = p->alloc(&p->d_wfirst, (size_t)n + 1, stream))) return fail(st);
+  if ((st = p->alloc(&p->d_total, 1, stream))) return fail(st);
+  if ((st = p->alloc((char**)&p->d_scan_tmp, scan_tmp_bytes(n), stream))) return fail(st);
+  if ((st = p->alloc((char**)&p->d_dummy, 4096, stream))) return fail(st);
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
+      p->n_cu = cus;
+  }
+
+  std::vector<const void*> host_ptrs(2 * (size_t)k);
+  for (int i = 0; i < k; ++i) {
+    host_ptrs[i] = colptr[i];
+    host_ptrs[k + i] = rowidx[i];
+  }
+  auto hipfail = [&](hipError_t e, const char* what) {
+    (void)hipGetLastError();
+    return fail(set_error(SPKADD_ERR_HIP, "%s: %s", what, hipGetErrorString(e)));
+  };
+  hipError_t e;
+  if ((e = hipMemcpyAsync(p->d_cp, host_ptrs.data(), 2 * (size_t)k * sizeof(void*), hipMemcpyHostToDevice, stream)))
+    return hipfail(e, "pointer upload");
+  if ((e = hipMemsetAsync(p->d_sum, 0, sizeof(PlanSummary), stream))) return hipfail(e, "memset");
+  if ((e = hipMemsetAsync(p->d_dummy, 0, 4096, stream))) return hipfail(e, "memset");
+  {
+    TraceScope t(p, "check_ptrs", stream);
+    launch_check_ptrs(p->pp, p->d_cp, p->d_ri, p->d_sum, stream);
+  }
+  if (o.flags & SPKADD_FLAG_VALIDATE) {
+    TraceScope t(p, "validate", stream);
+    launch_validate(p->pp, p->d_cp, p->d_ri, p->d_sum, stream);
+  }
+  {
+    TraceScope t(p, "bounds", stream);
+    launch_bounds(p->pp, p->d_cp, p->d_u, p->d_bin, p->d_colcnt, p->d_hist, p->d_sum, stream);
+  }
+  {
+    TraceScope t(p, "bin_scan", stream);
+    launch_bin_scan(nblk, p->d_hist, p->d_binoff, p->d_sum, stream);
+  }
+  {
+    TraceScope t(p, "bin_scatter", stream);
+    launch_bin_scatter(p->pp, p->d_bin, p->d_hist, p->d_binoff, p->d_list, stream);
+  }
+  {
+    TraceScope t(p, "win_scan", stream);
+    launch_win_scan(p->pp, p->d_list, p->d_binoff, p->d_u, p->d_wfirst, p->d_sum, stream);
+  }
+  if ((e = hipGetLastError())) return hipfail(e, "plan kernels");
+  if ((st = sync_summary(p, stream))) return fail(st);
+  if ((st = check_device_err(p))) return fail(st);
+  int acc = 0;
+  for (int b = 0; b < NBINS; ++b) {
+    p->bin_count[b] = p->h_sum.bin_count[b];
+    p->binoff[b] = acc;
+    acc += p->bin_count[b];
+  }
+  p->binoff[NBINS] = acc;
+  p->n_wcols = p->bin_count[BIN_WIN];
+  p->n_windows = p->n_wcols ? p->h_sum.n_windows : 0;
+  if ((st = check_lds(p))) return fail(st);
+  if (p->n_windows > 0) {
+    if ((st = build_windows(p, stream))) return fail(st);
+    if ((st = check_device_err(p))) return fail(st);
+  }
+  *out = p;
+  return SPKADD_OK;
+}
+
+spkadd_status spkadd_symbolic(spkadd_plan_t p, int32_t* colptr_c, int64_t* nnz_c, hipStream_t stream) {
+  g_last_error.clear();
+  if (!p || !colptr_c || !nnz_c) return set_error(SPKADD_ERR_INVALID, "NULL argument");
+  if (p->failed) return set_error(SPKADD_ERR_HIP, "plan failed earlier");
+  p->last_stream = stream;
+  KArgs a = base_args(p);
+  a.alpha_q = p->alpha_sym_q;
+  for (int b = BIN_W1; b < NBINS; ++b) {
+    const int cnt = b == BIN_WIN ? p->n_windows : p->bin_count[b];
+    if (cnt == 0) continue;
+    TraceScope t(p, hash_kernel_name(b, false), stream);
+    hipError_t e = launch_bin(p, b, false, a, stream);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p->failed = true;
+      return set_error(SPKADD_ERR_HIP, "symbolic launch (%s): %s", hash_kernel_name(b, false), hipGetErrorString(e));
+    }
+  }
+  if (p->n_windows > 0) {
+    TraceScope t(p, "win_colsum", stream);
+    launch_win_colsum(p->n_wcols, p->d_list + p->binoff[BIN_WIN], p->d_wfirst, p->d_win_cnt, p->d_colcnt,
+                      p->d_win_off, stream);
+  }
+  {
+    TraceScope t(p, "scan", stream);
+    launch_scan(p->d_colcnt, p->n, colptr_c, p->d_total, &p->d_sum->err, p->d_scan_tmp, stream);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    p->failed = true;
+    return set_error(SPKADD_ERR_HIP, "symbolic kernels: %s", hipGetErrorString(e));
+  }
+  long long total = 0;
+  HIP_TRY(hipMemcpyAsync(&total, p->d_total, sizeof(total), hipMemcpyDeviceToHost, stream));
+  spkadd_status st = sync_summary(p, stream);
+  if (st) return st;
+  if ((st = check_device_err(p))) return st;
+  if (total > INT_MAX) return set_error(SPKADD_ERR_OVERFLOW, "nnz(B) = %lld exceeds INT32_MAX", total);
+  p->colptr_c = colptr_c;
+  p->nnz_c = total;
+  p->sym_done = true;
+  *nnz_c = total;
+  return SPKADD_OK;
+}
+
+spkadd_status spkadd_numeric(spkadd_plan_t p, const void* const* values, int32_t* rowidx_c, void* values_c,
+                             hipStream_t stream) {
+  g_last_error.clear();
+  if (!p) return set_error(SPKADD_ERR_INVALID, "plan is NULL");
+  if (p->failed) return set_error(SPKADD_ERR_HIP, "plan failed earlier");
+  if (!p->sym_done) return set_error(SPKADD_ERR_STATE, "spkadd_symbolic has not run on this plan");
+  if (!values) return set_error(SPKADD_ERR_INVALID, "values is NULL");
+  if (p->nnz_c > 0 && (!rowidx_c || !values_c)) return set_error(SPKADD_ERR_INVALID, "output arrays are NULL");
+  p->last_stream = stream;
+  std::vector<const void*> hv((size_t)p->k);
+  for (int i = 0; i < p->k; ++i) hv[i] = values[i];
+  HIP_TRY(hipMemcpyAsync((void*)p->d_va, hv.data(), (size_t)p->k * sizeof(void*), hipMemcpyHostToDevice, stream));
+  KArgs a = base_args(p);
+  a.alpha_q = p->alpha_num_q;
+  a.colptr_c = p->colptr_c;
+  a.out_r = rowidx_c;
+  a.out_v = values_c;
+  for (int b = BIN_W1; b < NBINS; ++b) {
+    const int cnt = b == BIN_WIN ? p->n_windows : p->bin_count[b];
+    if (cnt == 0) continue;
+    TraceScope t(p, hash_kernel_name(b, true), stream);
+    hipError_t e = launch_bin(p, b, true, a, stream);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p->failed = true;
+      return set_error(SPKADD_ERR_HIP, "numeric launch (%s): %s", hash_kernel_name(b, true), hipGetErrorString(e));
+    }
+  }
+  return SPKADD_OK;
+}
+
+spkadd_status spkadd_free(spkadd_plan_t p) {
+  if (!p) return SPKADD_OK;
+  release_all(p);
+  clear_trace(p);
+  delete p;
+  return SPKADD_OK;
+}
+
+spkadd_status spkadd_get_stats(spkadd_plan_t p, spkadd_stats* out) {
+  if (!p || !out) return set_error(SPKADD_ERR_INVALID, "NULL argument");
+  spkadd_stats s{};
+  s.nnz_in = (int64_t)p->h_sum.nnz_in;
+  s.nnz_out = p->sym_done ? p->nnz_c : -1;
+  s.n_empty_cols = p->bin_count[BIN_EMPTY];
+  for (int b = BIN_W1; b <= BIN_W16; ++b) s.n_wave_cols += p->bin_count[b];
+  s.n_wg_cols = p->bin_count[BIN_G1] + p->bin_count[BIN_G2];
+  s.n_window_cols = p->n_wcols;
+  s.n_windows = p->n_windows;
+  s.window_levels = p->levels;
+  s.window_cap = p->pp.cap_in;
+  s.wave_max = p->pp.force_bin == 0 ? 1024 : p->pp.wave_max;
+  // device error flags raised by numeric passes since the last synchronisation
+  if (p->last_stream || true) {
+    int err = 0;
+    if (hipMemcpyAsync(&err, &p->d_sum->err, sizeof(int), hipMemcpyDeviceToHost, p->last_stream) == hipSuccess &&
+        hipStreamSynchronize(p->last_stream) == hipSuccess) {
+      p->h_sum.err = err;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  *out = s;
+  return check_device_err(p);
+}
+
+int32_t spkadd_trace_count(spkadd_plan_t p) { return p ? (int32_t)p->trace.size() : 0; }
+
+spkadd_status spkadd_trace_get(spkadd_plan_t p, int32_t idx, char* name, int32_t name_cap, float* ms) {
+  if (!p || idx < 0 || idx >= (int32_t)p->trace.size()) return set_error(SPKADD_ERR_INVALID, "bad trace index");
+  const TraceRec& r = p->trace[(size_t)idx];
+  if (name && name_cap > 0) {
+    strncpy(name, r.name, (size_t)name_cap - 1);
+    name[name_cap - 1] = 0;
+  }
+  if (ms) {
+    HIP_TRY(hipEventSynchronize(r.b));
+    HIP_TRY(hipEventElapsedTime(ms, r.a, r.b));
+  }
+  return SPKADD_OK;
+}
+
+spkadd_status spkadd_trace_reset(spkadd_plan_t p) {
+  if (!p) return set_error(SPKADD_ERR_INVALID, "plan is NULL");
+  clear_trace(p);
+  return SPKADD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+"""Helpers of the GPU parity tests: upload a batch, run SpKAdd through the C ABI,
+compare with the CPU oracle."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+import oracle
+import workloads
+
+F32_UNIT = 2.0 ** -24
+F64_UNIT = 2.0 ** -53
+
+
+def note(msg: str) -> None:
+    """Name the case before a GPU step, flushed, so a failing run says which one."""
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def to_device(batch: workloads.CSCBatch, dev="cuda:0"):
+    import torch
+    cps = [torch.from_numpy(np.ascontiguousarray(batch.colptr[i])).to(dev) for i in range(batch.k)]
+    ris = [torch.from_numpy(r).to(dev) for r in batch.rowidx]
+    vas = [torch.from_numpy(v).to(dev) for v in batch.vals]
+    return cps, ris, vas
+
+
+def run_gpu(batch: workloads.CSCBatch, opts=None, stats=False, device_out=False):
+    """(colptr int64, rowidx, values[, stats]) of B computed by the GPU library."""
+    import torch
+    from paper_2112_10223_amd import binding
+    cps, ris, vas = to_device(batch)
+    n = batch.n
+    dtype = binding.SPKADD_F64 if batch.vals[0].dtype == np.float64 else binding.SPKADD_F32
+    plan = binding.spkadd_plan(batch.m, n, cps, ris, dtype, opts)
+    try:
+        colptr_c = torch.empty(n + 1, dtype=torch.int32, device="cuda:0")
+        nnz = binding.spkadd_symbolic(plan, colptr_c)
+        rowidx_c = torch.empty(max(nnz, 1), dtype=torch.int32, device="cuda:0")[:nnz]
+        vals_c = torch.empty(max(nnz, 1), dtype=vas[0].dtype if vas else torch.float32, device="cuda:0")[:nnz]
+        binding.spkadd_numeric(plan, vas, rowidx_c, vals_c)
+        torch.cuda.synchronize()
+        st = binding.spkadd_get_stats(plan)
+    finally:
+        plan.free()
+    if device_out:
+        out = (colptr_c, rowidx_c, vals_c)
+    else:
+        out = (colptr_c.cpu().numpy().astype(np.int64), rowidx_c.cpu().numpy(), vals_c.cpu().numpy())
+    return (*out, st) if stats else out
+
+
+def value_bound(batch, ref):
+    """Per-entry tolerance k * u * sum|a| (u = 2^-24 for fp32, 2^-53 for fp64)."""
+    unit = F64_UNIT if batch.vals[0].dtype == np.float64 else F32_UNIT
+    return np.longdouble(batch.k) * np.longdouble(unit) * ref.abs
+
+
+def assert_matches(batch, got, ref, cols=None, exact_values=False):
+    """colptr and rowidx bit-exact; values bit-exact or within the tolerance."""
+    colptr, rowidx, vals = got[:3]
+    if cols is None:
+        assert np.array_equal(colptr, ref.colptr), "colptr differs"
+        assert np.array_equal(rowidx, ref.rowidx), "rowidx differs"
+        gv = vals
+    else:
+        cols = np.asarray(cols)
+        counts = colptr[cols + 1] - colptr[cols]
+        assert np.array_equal(counts, np.diff(ref.colptr)), "column counts differ"
+        sel = np.concatenate([np.arange(colptr[j], colptr[j + 1]) for j in cols]) if len(cols) else \
+            np.zeros(0, np.int64)
+        assert np.array_equal(rowidx[sel], ref.rowidx), "rows differ"
+        gv = vals[sel]
+    if exact_values:
+        assert np.array_equal(gv.astype(np.float64), ref.val.astype(np.float64)), "values differ"
+    else:
+        diff = np.abs(gv.astype(np.longdouble) - ref.val)
+        bound = value_bound(batch, ref)
+        bad = diff > bound
+        assert not bad.any(), f"{int(bad.sum())} values outside k*u*sum|a| (max excess {float((diff - bound).max())})"
+
+
+def check_properties(batch, colptr, rowidx):
+    """Invariants that hold at any size: colptr monotone from 0, rows in range and
+    strictly ascending per column, nnz(B) <= sum nnz(A_i), nnz(B(:,j)) >= max_i nnz(A_i(:,j))."""
+    n, m = batch.n, batch.m
+    assert colptr.shape == (n + 1,) and colptr[0] == 0
+    counts = np.diff(colptr)
+    assert (counts >= 0).all()
+    assert colptr[-1] == rowidx.shape[0] <= batch.nnz_in
+    for i in range(batch.k):
+        assert (counts >= np.diff(batch.colptr[i])).all()
+    if rowidx.shape[0]:
+        assert rowidx.min() >= 0 and rowidx.max() < m
+        d = np.diff(rowidx.astype(np.int64))
+        inner = np.ones(d.shape[0], bool)
+        b = colptr[1:-1] - 1
+        b = b[(b >= 0) & (b < d.shape[0])]
+        inner[b] = False
+        assert (d[inner] > 0).all(), "rows not strictly ascending within a column"
+
+
+def check_properties_device(batch, colptr_d, rowidx_d):
+    """check_properties with the row checks done on the device (large outputs)."""
+    import torch
+    n, m = batch.n, batch.m
+    colptr = colptr_d.cpu().numpy().astype(np.int64)
+    assert colptr.shape == (n + 1,) and colptr[0] == 0
+    counts = np.diff(colptr)
+    assert (counts >= 0).all()
+    assert colptr[-1] == rowidx_d.shape[0] <= batch.nnz_in
+    for i in range(batch.k):
+        assert (counts >= np.diff(batch.colptr[i])).all()
+    nnz = rowidx_d.shape[0]
+    if nnz:
+        assert int(rowidx_d.min()) >= 0 and int(rowidx_d.max()) < m
+        d = rowidx_d[1:] - rowidx_d[:-1]
+        inner = torch.ones(nnz - 1, dtype=torch.bool, device=rowidx_d.device)
+        b = colptr[1:-1] - 1
+        b = b[(b >= 0) & (b < nnz - 1)]
+        inner[torch.from_numpy(b).to(rowidx_d.device)] = False
+        assert bool((d[inner] > 0).all()), "rows not strictly ascending within a column"
+    return colptr
+
+
+def gather_columns(colptr, rowidx_d, vals_d, cols):
+    """Compact host copies (colptr of the selection, rows, values) of the listed output columns."""
+    import torch
+    cols = np.asarray(cols, dtype=np.int64)
+    counts = colptr[cols + 1] - colptr[cols]
+    sel = np.concatenate([np.arange(colptr[j], colptr[j + 1]) for j in cols]) if len(cols) else np.zeros(0, np.int64)
+    idx = torch.from_numpy(sel).to(rowidx_d.device)
+    sub_colptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    return sub_colptr, rowidx_d[idx].cpu().numpy(), vals_d[idx].cpu().numpy()

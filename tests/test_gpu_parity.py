@@ -1,0 +1,308 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+colptr and rowidx must match bit-exactly.  Integer-valued inputs must give
+bit-exact values.  Real values must lie within |c - c_ref| <= k * u * sum|a|
+(u = 2^-24 fp32, 2^-53 fp64).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_util import assert_matches, check_properties, note, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_10223_amd import binding
+    binding.lib()
+
+
+def _opts(**kw):
+    from paper_2112_10223_amd import binding
+    return binding.make_opts(**kw)
+
+
+@pytest.mark.parametrize("values", ["int32f", "f32", "int64f", "f64"])
+def test_config1(values):
+    note(f"config1 values={values}")
+    batch = workloads.config1(values=values)
+    got = run_gpu(batch)
+    ref = oracle.spkadd(batch)
+    assert_matches(batch, got, ref, exact_values=values.startswith("int"))
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_small_random(seed):
+    rng = np.random.default_rng(1000 + seed)
+    m = int(rng.integers(1, 300))
+    n = int(rng.integers(1, 120))
+    k = int(rng.integers(1, 9))
+    d = float(rng.choice([0.0, 0.5, 3.0, 20.0, 200.0]))
+    values = ["int32f", "f32", "f64", "int64f"][seed % 4]
+    note(f"small_random seed={seed} m={m} n={n} k={k} d={d} values={values}")
+    batch = workloads.er(m, n, k, d, seed=seed, values=values)
+    got = run_gpu(batch)
+    ref = oracle.spkadd(batch)
+    assert_matches(batch, got, ref, exact_values=values.startswith("int"))
+
+
+def _ragged_batch(seed=5, k=6, m=20000, values="int32f"):
+    """Columns whose sizes span every bin: empty, wave sub-bins, both workgroup
+    bins and the window bin."""
+    sizes = [0, 1, 3, 10, 40, 64, 65, 100, 170, 200, 250, 300, 500, 700, 900, 1100, 1500, 2500, 3000, 3500,
+             6000, 9000]
+    n = len(sizes) * 3
+    per = np.array([sizes[j % len(sizes)] for j in range(n)], dtype=np.float64) / k
+    masks_cp = np.zeros((k, n + 1), np.int32)
+    rows, vals = [[] for _ in range(k)], [[] for _ in range(k)]
+    rng = np.random.default_rng(seed)
+    for j in range(n):
+        for i in range(k):
+            c = int(min(m, rng.poisson(per[j]) if per[j] > 0 else 0))
+            r = np.sort(rng.choice(m, size=c, replace=False)).astype(np.int32)
+            rows[i].append(r)
+            if values == "int32f":
+                vals[i].append(rng.integers(-3, 4, size=c).astype(np.float32))
+            else:
+                vals[i].append(((rng.integers(0, 1 << 24, size=c) - (1 << 23)) * 2.0 ** -23).astype(np.float32))
+            masks_cp[i, j + 1] = masks_cp[i, j] + c
+    return workloads.CSCBatch(m, n, masks_cp, [np.concatenate(r) for r in rows], [np.concatenate(v) for v in vals])
+
+
+@pytest.mark.parametrize("force_bin,window_cap", [(-1, 0), (0, 0), (1, 0), (2, 0), (2, 64), (-1, 128), (1, 700),
+                                                  (2, 1000)])
+def test_forced_bins(force_bin, window_cap):
+    note(f"forced_bins force_bin={force_bin} window_cap={window_cap}")
+    batch = _ragged_batch()
+    got = run_gpu(batch, _opts(force_bin=force_bin, window_cap=window_cap), stats=True)
+    ref = oracle.spkadd(batch)
+    assert_matches(batch, got, ref, exact_values=True)
+    st = got[3]
+    if force_bin == 2:
+        assert st["n_window_cols"] == batch.n - st["n_empty_cols"]
+
+
+def test_sliding_windows_match_plain():
+    """Forcing the sliding hash must reproduce the plain result bit for bit on
+    colptr / rowidx (Algorithms 7-8 change only where the table lives)."""
+    note("sliding_windows_match_plain")
+    batch = workloads.er(50000, 300, 16, 40.0, seed=21, values="int32f")
+    plain = run_gpu(batch)
+    slid = run_gpu(batch, _opts(force_bin=2, window_cap=96), stats=True)
+    assert slid[3]["n_windows"] > batch.n
+    assert np.array_equal(plain[0], slid[0]) and np.array_equal(plain[1], slid[1])
+    assert np.array_equal(plain[2], slid[2])
+
+
+def test_degenerate_hash():
+    note("degenerate_hash")
+    batch = workloads.er(3000, 200, 5, 30.0, seed=8, values="int32f")
+    got = run_gpu(batch, _opts(hash_mode=1))
+    ref = oracle.spkadd(batch)
+    assert_matches(batch, got, ref, exact_values=True)
+    got = run_gpu(batch, _opts(hash_mode=1, force_bin=2, window_cap=64))
+    assert_matches(batch, got, ref, exact_values=True)
+
+
+def test_load_factors_and_wave_limit():
+    note("load_factors_and_wave_limit")
+    batch = _ragged_batch(seed=9, values="f32")
+    ref = oracle.spkadd(batch)
+    for kw in [dict(load_factor_sym=0.9, load_factor_num=0.5), dict(load_factor_sym=0.2, load_factor_num=0.25),
+               dict(wave_max=64), dict(wave_max=256, window_fill=0.3)]:
+        got = run_gpu(batch, _opts(**kw))
+        assert_matches(batch, got, ref)
+
+
+def test_edge_shapes():
+    import torch
+    note("edge_shapes")
+    # k = 1: B is A_1 itself
+    b1 = workloads.er(500, 300, 1, 6.0, seed=2, values="f32")
+    got = run_gpu(b1)
+    assert np.array_equal(got[0], b1.colptr[0].astype(np.int64))
+    assert np.array_equal(got[1], b1.rowidx[0]) and np.array_equal(got[2], b1.vals[0])
+    # m = 1 (every column has at most one row), n = 1 (one column)
+    for m, n, d in [(1, 400, 0.7), (700, 1, 300.0), (2, 3, 1.0)]:
+        b = workloads.er(m, n, 7, d, seed=3, values="int32f")
+        assert_matches(b, run_gpu(b), oracle.spkadd(b), exact_values=True)
+    # all-empty inputs
+    b = workloads.er(100, 50, 3, 0.0, seed=4, values="f32")
+    got = run_gpu(b)
+    assert got[0].sum() == 0 and got[1].shape == (0,)
+    # fully dense columns: every input holds every row
+    mask = np.ones((64, 5), bool)
+    vals = [np.full((64, 5), float(i + 1), np.float32) for i in range(4)]
+    b = workloads.from_dense([mask] * 4, vals)
+    assert_matches(b, run_gpu(b), oracle.spkadd(b), exact_values=True)
+    # n = 0 and m = 0
+    from paper_2112_10223_amd import binding
+    e = [torch.zeros(1, dtype=torch.int32, device="cuda:0")]
+    plan = binding.spkadd_plan(10, 0, e, [None], binding.SPKADD_F32)
+    cp = torch.empty(1, dtype=torch.int32, device="cuda:0")
+    assert binding.spkadd_symbolic(plan, cp) == 0 and int(cp.item()) == 0
+    plan.free()
+    e = [torch.zeros(4, dtype=torch.int32, device="cuda:0")] * 2
+    plan = binding.spkadd_plan(0, 3, e, [None, None], binding.SPKADD_F32)
+    cp = torch.empty(4, dtype=torch.int32, device="cuda:0")
+    assert binding.spkadd_symbolic(plan, cp) == 0 and cp.cpu().tolist() == [0, 0, 0, 0]
+    binding.spkadd_numeric(plan, [None, None], None, None)
+    plan.free()
+
+
+def test_same_row_everywhere_and_large_k():
+    note("same_row_everywhere_and_large_k")
+    k, m, n = 200, 1000, 40
+    cp = np.tile(np.arange(n + 1, dtype=np.int32), (k, 1))
+    rows = [np.full(n, 7, np.int32) for _ in range(k)]
+    vals = [np.full(n, 1.0, np.float32) for _ in range(k)]
+    b = workloads.CSCBatch(m, n, cp, rows, vals)
+    got = run_gpu(b)
+    assert np.array_equal(got[0], np.arange(n + 1)) and (got[1] == 7).all() and (got[2] == k).all()
+    for fb in (1, 2):
+        got = run_gpu(b, _opts(force_bin=fb, window_cap=64))
+        assert np.array_equal(got[0], np.arange(n + 1)) and (got[1] == 7).all() and (got[2] == k).all()
+
+
+def test_permutation_invariance():
+    note("permutation_invariance")
+    batch = workloads.er(5000, 500, 12, 25.0, seed=17, values="int32f")
+    base = run_gpu(batch)
+    perm = np.random.default_rng(3).permutation(batch.k)
+    other = run_gpu(batch.select(perm))
+    for x, y in zip(base, other):
+        assert np.array_equal(x, y)
+
+
+def test_numeric_rerun_new_values():
+    """spkadd_numeric may run again with new values on the same pattern."""
+    import torch
+    from paper_2112_10223_amd import binding
+    from tests.gpu_util import to_device
+    note("numeric_rerun_new_values")
+    b1 = workloads.er(4000, 300, 6, 30.0, seed=31, values="int32f")
+    b2 = workloads.CSCBatch(b1.m, b1.n, b1.colptr, b1.rowidx, [(v * 2 + 1).astype(np.float32) for v in b1.vals])
+    cps, ris, vas1 = to_device(b1)
+    _, _, vas2 = to_device(b2)
+    plan = binding.spkadd_plan(b1.m, b1.n, cps, ris, binding.SPKADD_F32)
+    cp = torch.empty(b1.n + 1, dtype=torch.int32, device="cuda:0")
+    nnz = binding.spkadd_symbolic(plan, cp)
+    r = torch.empty(nnz, dtype=torch.int32, device="cuda:0")
+    v = torch.empty(nnz, dtype=torch.float32, device="cuda:0")
+    for b, vas in ((b1, vas1), (b2, vas2), (b1, vas1)):
+        binding.spkadd_numeric(plan, vas, r, v)
+        torch.cuda.synchronize()
+        ref = oracle.spkadd(b)
+        assert_matches(b, (cp.cpu().numpy().astype(np.int64), r.cpu().numpy(), v.cpu().numpy()), ref,
+                       exact_values=True)
+    plan.free()
+
+
+def test_state_and_validation_errors():
+    import torch
+    from paper_2112_10223_amd import binding
+    from tests.gpu_util import to_device
+    note("state_and_validation_errors")
+    b = workloads.er(100, 20, 2, 5.0, seed=1)
+    cps, ris, vas = to_device(b)
+    plan = binding.spkadd_plan(b.m, b.n, cps, ris, binding.SPKADD_F32)
+    with pytest.raises(binding.SpkaddError) as ei:
+        binding.spkadd_numeric(plan, vas, torch.empty(1, dtype=torch.int32, device="cuda:0"),
+                               torch.empty(1, device="cuda:0"))
+    assert ei.value.status == binding.SPKADD_ERR_STATE
+    plan.free()
+    # an unsorted column is rejected when validation is on
+    bad = [r.clone() for r in ris]
+    j = int(np.argmax(np.diff(b.colptr[0])))
+    s = int(b.colptr[0, j])
+    bad[0][s], bad[0][s + 1] = ris[0][s + 1].item(), ris[0][s].item()
+    with pytest.raises(binding.SpkaddError) as ei:
+        binding.spkadd_plan(b.m, b.n, cps, bad, binding.SPKADD_F32, _opts(flags=binding.SPKADD_FLAG_VALIDATE))
+    assert ei.value.status == binding.SPKADD_ERR_INVALID
+    # row out of range
+    bad = [r.clone() for r in ris]
+    bad[1][0] = b.m
+    with pytest.raises(binding.SpkaddError):
+        binding.spkadd_plan(b.m, b.n, cps, bad, binding.SPKADD_F32, _opts(flags=binding.SPKADD_FLAG_VALIDATE))
+    # valid input passes validation
+    binding.spkadd_plan(b.m, b.n, cps, ris, binding.SPKADD_F32, _opts(flags=binding.SPKADD_FLAG_VALIDATE)).free()
+
+
+def test_trace_records_kernels():
+    from paper_2112_10223_amd import binding
+    import torch
+    from tests.gpu_util import to_device
+    note("trace_records_kernels")
+    b = workloads.config1()
+    cps, ris, vas = to_device(b)
+    plan = binding.spkadd_plan(b.m, b.n, cps, ris, binding.SPKADD_F32, _opts(flags=binding.SPKADD_FLAG_TRACE))
+    cp = torch.empty(b.n + 1, dtype=torch.int32, device="cuda:0")
+    nnz = binding.spkadd_symbolic(plan, cp)
+    r = torch.empty(nnz, dtype=torch.int32, device="cuda:0")
+    v = torch.empty(nnz, dtype=torch.float32, device="cuda:0")
+    binding.spkadd_numeric(plan, vas, r, v)
+    tr = binding.spkadd_trace(plan)
+    names = [t[0] for t in tr]
+    assert "bounds" in names and any(x.startswith("sym_") for x in names) and any(x.startswith("num_") for x in names)
+    assert all(ms >= 0 for _, ms in tr)
+    plan.free()
+
+
+# ---- full-size workloads: properties on every column, the oracle on sampled columns ----
+def _sample_cols(n, count, seed):
+    rng = np.random.default_rng(seed)
+    cols = np.unique(np.concatenate([[0, n - 1], rng.choice(n, size=min(count, n), replace=False)]))
+    return cols.astype(np.int64)
+
+
+def _full_check(batch, got, cols, exact=False):
+    """got = (colptr, rowidx, values) on the device."""
+    from tests.gpu_util import check_properties_device, gather_columns
+    colptr = check_properties_device(batch, got[0], got[1])
+    sub = gather_columns(colptr, got[1], got[2], cols)
+    ref = oracle.spkadd(batch, cols=cols)
+    assert_matches(batch, sub, ref, exact_values=exact)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("values", ["f32", "f64"])
+def test_config2_full(values):
+    note(f"config2 full values={values}")
+    batch = workloads.config2(values=values)
+    got = run_gpu(batch, stats=True, device_out=True)
+    assert got[3]["n_wave_cols"] > 0
+    _full_check(batch, got, _sample_cols(batch.n, 3000, 1))
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(600)
+def test_config3_full():
+    note("config3 full (R-MAT scale 20, k=64)")
+    batch = workloads.config3()
+    got = run_gpu(batch, stats=True, device_out=True)
+    st = got[3]
+    print("config3 stats", st, flush=True)
+    assert st["n_window_cols"] > 0
+    # sample: heavy columns (largest u) plus random ones
+    u = sum(np.diff(batch.colptr[i]).astype(np.int64) for i in range(batch.k))
+    heavy = np.argsort(u)[-40:]
+    cols = np.unique(np.concatenate([heavy, _sample_cols(batch.n, 2000, 3)]))
+    _full_check(batch, got, cols)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("window", [0, 524288])
+def test_config4_full(window):
+    note(f"config4 full window={window}")
+    batch = workloads.config4(window=window)
+    got = run_gpu(batch, stats=True, device_out=True)
+    assert got[3]["n_window_cols"] == batch.n
+    _full_check(batch, got, _sample_cols(batch.n, 40, 4))
