@@ -70,6 +70,11 @@ typedef enum spkadd_dtype { SPKADD_F32 = 0, SPKADD_F64 = 1 } spkadd_dtype;
 #define SPKADD_BIN_WG 1     /* one workgroup per column (columns with u_j <= window_cap) */
 #define SPKADD_BIN_WINDOW 2 /* sliding-hash row windows for every non-empty column */
 
+/* opts.accum_mode */
+#define SPKADD_ACCUM_AUTO 0
+#define SPKADD_ACCUM_HASH 1
+#define SPKADD_ACCUM_BITMAP 2
+
 /* Tuning and test options.  Zero-initialised fields (or opts == NULL) mean "auto". */
 typedef struct spkadd_opts {
   uint32_t flags;        /* SPKADD_FLAG_* */
@@ -82,7 +87,11 @@ typedef struct spkadd_opts {
   float load_factor_sym; /* max (input entries / table slots) of symbolic tables; 0 = auto */
   float load_factor_num; /* max (output entries / table slots) of numeric tables, <= 0.5; 0 = auto */
   float window_fill;     /* target fill of a row window relative to window_cap; 0 = auto */
-  int32_t reserved[4];
+  int32_t accum_mode;    /* wave bins: 0 = auto (bitmap where dense enough, else hash),
+                            1 = hash tables only, 2 = bitmap wherever it fits (m <= 131072) */
+  float bitmap_ratio;    /* auto mode: use the bitmap when ceil(m / 8192) <= bitmap_ratio * E,
+                            E = ceil(u_max / 64) of the bin; 0 = default (1.0) */
+  int32_t reserved[2];
 } spkadd_opts;
 
 typedef struct spkadd_plan_s* spkadd_plan_t;

@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OOM", 3: "HIP", 4: "STATE", 5: "OVERF
 SPKADD_F32, SPKADD_F64 = 0, 1
 SPKADD_FLAG_VALIDATE, SPKADD_FLAG_TRACE = 1, 2
 SPKADD_BIN_AUTO, SPKADD_BIN_WAVE, SPKADD_BIN_WG, SPKADD_BIN_WINDOW = -1, 0, 1, 2
+SPKADD_ACCUM_AUTO, SPKADD_ACCUM_HASH, SPKADD_ACCUM_BITMAP = 0, 1, 2
 
 
 class SpkaddError(RuntimeError):
@@ -31,7 +32,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("force_bin", ctypes.c_int32), ("window_cap", ctypes.c_int32),
                 ("hash_mode", ctypes.c_int32), ("wave_max", ctypes.c_int32), ("load_factor_sym", ctypes.c_float),
                 ("load_factor_num", ctypes.c_float), ("window_fill", ctypes.c_float),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("accum_mode", ctypes.c_int32), ("bitmap_ratio", ctypes.c_float), ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):

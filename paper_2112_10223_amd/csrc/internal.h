@@ -84,7 +84,9 @@ struct KArgs {
   int upw;                // wave pipeline: units per wavefront
   // LDS layout (bytes, per wave for the wave kernels, per block for the workgroup kernels)
   int ts_max;             // table slots available
-  int off_P, off_adj, off_adjv, off_hist, off_match, slice_bytes;
+  int off_P, off_adj, off_adjv, off_hist, off_match, off_mark, slice_bytes;
+  int bm_nq;              // wave bitmap mode: bitmap rows of 256 words (0 = hash mode)
+  int off_bm, off_pre, off_bvals;
 };
 
 // ---- plan kernels (plan_kernels.hip) ----
@@ -138,7 +140,7 @@ hipError_t launch_hash(int bin, bool numeric, bool f64, const KArgs& a, const in
 const char* hash_kernel_name(int bin, bool numeric);
 // Pipelined wave-bin kernels (wave_kernels.hip): k <= 64 and numeric load factor 1/2.
 bool wave_pipe_ok(int k, int alpha_num_q);
-void lds_layout_pipe(int bin, bool numeric, int vbytes, int ts_max, KArgs& a);
+void lds_layout_pipe(int bin, bool numeric, int vbytes, int ts_max, int bm_nq, KArgs& a);
 hipError_t launch_wave_pipe(int bin, bool numeric, bool f64, const KArgs& a, const int* d_list, int nunits,
                             hipStream_t s);
 int max_lds_bytes();

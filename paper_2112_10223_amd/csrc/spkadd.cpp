@@ -258,14 +258,16 @@ int ktop_of(int k) {
   return t;
 }
 
+bool layout_bin(const spkadd_plan_s* p, int b, bool numeric, KArgs& a);
+
 spkadd_status check_lds(spkadd_plan_s* p) {
-  const int vb = p->dtype == SPKADD_F64 ? 8 : 4;
   const int lmax = max_lds_bytes();
   for (int b = BIN_W1; b < NBINS; ++b) {
-    if (p->bin_count[b] == 0) continue;
+    const int cnt = b == BIN_WIN ? p->n_windows : p->bin_count[b];
+    if (cnt == 0) continue;
     for (int numeric = 0; numeric < 2; ++numeric) {
       KArgs a{};
-      lds_layout(b, numeric != 0, vb, p->k, numeric ? p->ts_num[b] : p->ts_sym[b], a);
+      layout_bin(p, b, numeric != 0, a);
       const long long bytes = (long long)a.slice_bytes * bin_units_per_block(b);
       if (bytes > lmax)
         return set_error(SPKADD_ERR_UNSUPPORTED,
@@ -419,16 +421,36 @@ spkadd_status build_windows(spkadd_plan_s* p, hipStream_t s) {
 
 bool is_wave(int b) { return b >= BIN_W1 && b <= BIN_W16; }
 
+// Bitmap rows (of 256 words) for a wave bin, or 0 for hash tables.
+int bitmap_rows(const spkadd_plan_s* p, int b) {
+  if (!is_wave(b) || p->opts.accum_mode == SPKADD_ACCUM_HASH) return 0;
+  const long long nq = ((long long)p->m + 8191) / 8192;
+  if (nq < 1 || nq > 16) return 0;
+  if (p->opts.accum_mode == SPKADD_ACCUM_BITMAP) return (int)nq;
+  const float ratio = p->opts.bitmap_ratio > 0 ? p->opts.bitmap_ratio : 1.0f;
+  return nq <= ratio * wave_bin_E(b) ? (int)nq : 0;
+}
+
+// LDS layout of bin b for a phase; returns whether the pipelined wave kernel runs it.
+bool layout_bin(const spkadd_plan_s* p, int b, bool numeric, KArgs& a) {
+  const int vb = p->dtype == SPKADD_F64 ? 8 : 4;
+  const int ts = numeric ? p->ts_num[b] : p->ts_sym[b];
+  if (is_wave(b) && wave_pipe_ok(p->k, p->alpha_num_q)) {
+    lds_layout_pipe(b, numeric, vb, ts, bitmap_rows(p, b), a);
+    return true;
+  }
+  lds_layout(b, numeric, vb, p->k, ts, a);
+  a.bm_nq = 0;
+  return false;
+}
+
 // Launches the symbolic or numeric kernel of bin b.
 hipError_t launch_bin(spkadd_plan_s* p, int b, bool numeric, KArgs& a, hipStream_t s) {
   const int cnt = b == BIN_WIN ? p->n_windows : p->bin_count[b];
   if (cnt == 0) return hipSuccess;
   const bool f64 = p->dtype == SPKADD_F64;
-  const int vb = f64 ? 8 : 4;
-  const int ts = numeric ? p->ts_num[b] : p->ts_sym[b];
   const int* list = b == BIN_WIN ? nullptr : p->d_list + p->binoff[b];
-  if (is_wave(b) && wave_pipe_ok(p->k, p->alpha_num_q)) {
-    lds_layout_pipe(b, numeric, vb, ts, a);
+  if (layout_bin(p, b, numeric, a)) {
     const int block_lds = a.slice_bytes * WAVES_PER_BLOCK;
     int bpc = max_lds_bytes() / block_lds;
     if (bpc > 8) bpc = 8;
@@ -438,7 +460,6 @@ hipError_t launch_bin(spkadd_plan_s* p, int b, bool numeric, KArgs& a, hipStream
     a.upw = (int)(upw < 1 ? 1 : upw > 64 ? 64 : upw);
     return launch_wave_pipe(b, numeric, f64, a, list, cnt, s);
   }
-  lds_layout(b, numeric, vb, p->k, ts, a);
   return launch_hash(b, numeric, f64, a, list, cnt, s);
 }
 
@@ -487,6 +508,9 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
     return set_error(SPKADD_ERR_INVALID, "load_factor_num must be in [0, 0.5]");
   if (!(o.window_fill >= 0.f && o.window_fill <= 1.f))
     return set_error(SPKADD_ERR_INVALID, "window_fill must be in [0, 1]");
+  if (o.accum_mode < 0 || o.accum_mode > 2) return set_error(SPKADD_ERR_INVALID, "bad accum_mode %d", o.accum_mode);
+  if (!(o.bitmap_ratio >= 0.f && o.bitmap_ratio <= 64.f))
+    return set_error(SPKADD_ERR_INVALID, "bitmap_ratio must be in [0, 64]");
 
   auto* p = new (std::nothrow) spkadd_plan_s();
   if (!p) return set_error(SPKADD_ERR_OOM, "host allocation failed");

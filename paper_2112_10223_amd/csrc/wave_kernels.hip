@@ -18,28 +18,23 @@
 
 namespace spk {
 
-// Entry addresses of one unit: lockstep binary searches over the segment prefix P
-// (all E searches advance together, one LDS round trip per step).
+// Entry addresses of one unit.  Every non-empty segment i writes its id at byte
+// P[i] of a mark array; a running max-scan over the marks (DPP, carried from one
+// chunk of 64 entries to the next) then gives each entry its segment.  Lanes past
+// the end re-read the unit's last entry, so no load is masked off.
 template <int E, bool NUM, typename V>
-__device__ __forceinline__ void issue_unit_loads(const KArgs& a, const int* P, const long long* adj,
+__device__ __forceinline__ void issue_unit_loads(const KArgs& a, unsigned char* base, const long long* adj,
                                                  const long long* adjv, int u, int (&rows)[E], V (&vals)[E]) {
   const int lane = lane_id();
+  signed char* marks = (signed char*)(base + a.off_mark);
   int seg[E];
+  int carry = 0;
 #pragma unroll
-  for (int t = 0; t < E; ++t) seg[t] = 0;
-  for (int step = a.ktop; step > 0; step >>= 1) {
-    int pv[E];
-#pragma unroll
-    for (int t = 0; t < E; ++t) {
-      const int c = seg[t] + step;
-      pv[t] = P[c < a.k ? c : a.k - 1];
-    }
-#pragma unroll
-    for (int t = 0; t < E; ++t) {
-      const int c = seg[t] + step;
-      const int e = min(lane + 64 * t, u - 1);
-      if (c < a.k && pv[t] <= e) seg[t] = c;
-    }
+  for (int t = 0; t < E; ++t) {
+    const int mk = marks[64 * t + lane];
+    const int sc = max(wave_scan_max(mk), carry);
+    carry = readlane(sc, 63);
+    seg[t] = sc;
   }
   long long ar[E], av[E];
 #pragma unroll
@@ -50,7 +45,7 @@ __device__ __forceinline__ void issue_unit_loads(const KArgs& a, const int* P, c
   const long long dummy = (long long)a.dummy;
 #pragma unroll
   for (int t = 0; t < E; ++t) {
-    const int e = min(lane + 64 * t, u - 1);  // masked lanes re-read the unit's last entry
+    const int e = min(lane + 64 * t, u - 1);
     rows[t] = gload<int>(u > 0 ? ar[t] + 4LL * e : dummy);
     if (NUM) vals[t] = gload<V>(u > 0 ? av[t] + (long long)sizeof(V) * e : dummy);
   }
@@ -70,138 +65,153 @@ __device__ __forceinline__ void issue_meta_loads(const KArgs& a, long long cpp, 
 }
 
 // Segment table of a unit from its column pointers; returns u.
-template <bool NUM, typename V>
-__device__ __forceinline__ int build_unit_meta(const KArgs& a, long long rip, long long vap, int s, int e, int* P,
-                                               long long* adj, long long* adjv, bool null_unit) {
+template <int E, bool NUM, typename V>
+__device__ __forceinline__ int build_unit_meta(const KArgs& a, unsigned char* base, long long rip, long long vap,
+                                               int s, int e, long long* adj, long long* adjv, bool null_unit) {
   const int lane = lane_id();
   const int len = (lane < a.k && !null_unit) ? e - s : 0;
   const int incl = wave_scan_add(len);
   const int ex = incl - len;
   if (lane < a.k) {
-    P[lane] = ex;
     adj[lane] = rip + 4LL * (s - ex);
     if (NUM) adjv[lane] = vap + (long long)sizeof(V) * (s - ex);
   }
+  // marks: -1 everywhere (64 E bytes, 16 per lane), then segment ids at the starts
+  signed char* marks = (signed char*)(base + a.off_mark);
+  if (lane < 4 * E) reinterpret_cast<int4*>(marks)[lane] = make_int4(-1, -1, -1, -1);
+  wave_sync();
+  if (len > 0) marks[ex] = (signed char)lane;
   return readlane(incl, 63);
 }
 
-// Algorithm 6 on E entries per lane with batched claims; returns this lane's new keys.
-template <int E>
-__device__ __forceinline__ int sym_insert_batch(int* T, int TS, int mode, int u, const int (&rows)[E], int* err) {
+// Value accumulation without LDS floating-point atomics (which are slow on this
+// hardware): a compare-and-swap loop on the value's bit pattern.
+template <typename V>
+__device__ __forceinline__ void lds_add_cas(V* p, V v) {
+  if constexpr (sizeof(V) == 4) {
+    unsigned* q = reinterpret_cast<unsigned*>(p);
+    unsigned old = *q;
+    for (;;) {
+      const unsigned nv = __float_as_uint(__uint_as_float(old) + (float)v);
+      const unsigned prev = atomicCAS(q, old, nv);
+      if (prev == old) break;
+      old = prev;
+    }
+  } else {
+    unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+    unsigned long long old = *q;
+    for (;;) {
+      const unsigned long long nv =
+          (unsigned long long)__double_as_longlong(__longlong_as_double((long long)old) + (double)v);
+      const unsigned long long prev = atomicCAS(q, old, nv);
+      if (prev == old) break;
+      old = prev;
+    }
+  }
+}
+
+// Algorithms 5 and 6 on E entries per lane of a wavefront-private table, with
+// linear probing.  The entries of one index t are resolved before those of t+1.  A
+// row's probe sequence depends only on the row, so concurrent inserts of the same
+// row meet in the same slot.  NUM: the lane whose claim created the slot stores the
+// value (plain store).  A lane that finds its row already there adds with a
+// compare-and-swap loop.  The table belongs to one wavefront, so program order is
+// the order in LDS, and the store comes first.  SYM counts first claims.
+// Returns this lane's new keys.
+template <int E, bool NUM, typename V>
+__device__ __forceinline__ int insert_batch(int* K, V* Vt, int TS, int mode, int u, const int (&rows)[E],
+                                            const V (&vals)[E], int* err) {
   const int lane = lane_id();
-  int slot[E];
-  bool act[E];
+  int newc = 0;
 #pragma unroll
   for (int t = 0; t < E; ++t) {
-    act[t] = lane + 64 * t < u;
-    slot[t] = hash_slot(rows[t], TS, mode);
-  }
-  int newc = 0;
-  for (int probe = 0; probe < TS; ++probe) {
-    int old[E];
-#pragma unroll
-    for (int t = 0; t < E; ++t) old[t] = act[t] ? atomicCAS(&T[slot[t]], -1, rows[t]) : -2;
-    bool more = false;
-#pragma unroll
-    for (int t = 0; t < E; ++t) {
-      if (act[t]) {
-        if (old[t] == -1) {
-          ++newc;
-          act[t] = false;
-        } else if (old[t] == rows[t]) {
-          act[t] = false;
-        } else {
-          slot[t] = slot[t] + 1 == TS ? 0 : slot[t] + 1;
-          more = true;
-        }
+    const bool in = lane + 64 * t < u;
+    const int r = rows[t];
+    int s = hash_slot(r, TS, mode);
+    int old = -2;
+    if (in) {
+      int probe = 0;
+      for (; probe < TS; ++probe) {
+        old = atomicCAS(&K[s], -1, r);
+        if (old == -1 || old == r) break;
+        s = s + 1 == TS ? 0 : s + 1;
       }
+      if (probe == TS) atomicOr(err, ERR_PROBE);
     }
-    if (ballot(more) == 0) return newc;
+    const bool own = in && old == -1;
+    newc += own ? 1 : 0;
+    if (NUM) {
+      // every lane of index t has its slot now: owners store, then the others add
+      if (own) Vt[s] = vals[t];
+      wave_sync();
+      if (in && old == r) lds_add_cas<V>(&Vt[s], vals[t]);
+      wave_sync();
+    }
   }
-  atomicOr(err, ERR_PROBE);
   return newc;
 }
 
-// Algorithm 5 on E entries per lane with batched claims.
-template <int E, typename V>
-__device__ __forceinline__ void num_insert_batch(int* K, V* Vt, int TS, int mode, int u, const int (&rows)[E],
-                                                 const V (&vals)[E], int* err) {
-  const int lane = lane_id();
-  int slot[E];
-  bool act[E];
-#pragma unroll
-  for (int t = 0; t < E; ++t) {
-    act[t] = lane + 64 * t < u;
-    slot[t] = hash_slot(rows[t], TS, mode);
-  }
-  for (int probe = 0; probe < TS; ++probe) {
-    int old[E];
-#pragma unroll
-    for (int t = 0; t < E; ++t) old[t] = act[t] ? atomicCAS(&K[slot[t]], -1, rows[t]) : -2;
-    bool more = false;
-#pragma unroll
-    for (int t = 0; t < E; ++t) {
-      if (act[t]) {
-        if (old[t] == -1 || old[t] == rows[t]) {
-          atomicAdd(&Vt[slot[t]], vals[t]);
-          act[t] = false;
-        } else {
-          slot[t] = slot[t] + 1 == TS ? 0 : slot[t] + 1;
-          more = true;
-        }
-      }
-    }
-    if (ballot(more) == 0) return;
-  }
-  atomicOr(err, ERR_PROBE);
-}
-
-// Numeric work of one unit: table, accumulation, bucket-rank sort, write-out.
+// Numeric work of one unit: table, accumulation, compaction, bucket-rank sort,
+// write-out.  The key and value arrays have 64 extra sink slots after ts_max; lanes
+// without an entry write there, so no store is predicated.
 template <int E, typename V>
 __device__ __forceinline__ void num_unit(const KArgs& a, unsigned char* base, int u, int cnt, int o0,
                                          const int (&rows)[E], const V (&vals)[E]) {
-  constexpr int NCH = 2 * E;  // table chunks of 64 slots at load factor 1/2
+  constexpr int NCH = 2 * E;  // 64-slot table chunks at load factor 1/2
+  constexpr int RANK_UNROLL = 4;
   const int lane = lane_id();
   int* K = (int*)base;
-  V* Vt = (V*)(base + a.ts_max * 4);
-  int* hist = (int*)(base + a.off_hist);
+  V* Vt = (V*)(base + (a.ts_max + 64) * 4);
+  int* hist = (int*)(base + a.off_hist);  // 256 buckets + sink
+  const int sink = a.ts_max + lane;
   int TS = slots_for(cnt, a.alpha_q);
   if (TS > NCH * 64) TS = NCH * 64;
 #pragma unroll
-  for (int c = 0; c < NCH; ++c) {
-    const int s = 64 * c + lane;
-    if (s < TS) {
-      K[s] = -1;
-      Vt[s] = V(0);
-    }
-  }
+  for (int c = 0; c < NCH; ++c) K[64 * c + lane] = -1;
   reinterpret_cast<int4*>(hist)[lane] = make_int4(0, 0, 0, 0);
   wave_sync();
-  num_insert_batch<E, V>(K, Vt, TS, a.hash_mode, u, rows, vals, a.err);
+  insert_batch<E, true, V>(K, Vt, TS, a.hash_mode, u, rows, vals, a.err);
   wave_sync();
+  // compaction of the valid slots to A = [0, nc), slot order
   int kk[NCH];
   V vv[NCH];
-  int mn = INT_MAX, mx = -1;
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
-    const int s = 64 * c + lane;
-    kk[c] = s < TS ? K[s] : -1;
-    vv[c] = s < TS ? Vt[s] : V(0);
+    kk[c] = K[64 * c + lane];
+    vv[c] = Vt[64 * c + lane];
   }
+  int nc = 0, mn = INT_MAX, mx = -1;
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
-    if (kk[c] >= 0) {
-      mn = min(mn, kk[c]);
-      mx = max(mx, kk[c]);
-    }
+    const bool ok = kk[c] != -1;
+    const uint64_t m = ballot(ok);
+    const int dst = ok ? nc + mbcnt(m) : sink;
+    K[dst] = kk[c];
+    Vt[dst] = vv[c];
+    nc += __popcll(m);
+    mn = min(mn, ok ? kk[c] : INT_MAX);
+    mx = max(mx, ok ? kk[c] : -1);
+  }
+  if (nc != cnt) {
+    if (lane == 0) atomicOr(a.err, ERR_COUNT);
+    nc = 0;  // write nothing for this unit
   }
   mn = wave_total_min(mn);
   mx = wave_total_max(mx);
   const int bits = mx >= mn ? ceil_log2(mx - mn + 1) : 0;
   const int sh = bits > 8 ? bits - 8 : 0;
+  wave_sync();
+  // bucket histogram of A (bucket = top 8 bits of key - mn)
+  int ka[E], dg[E];
+  V va[E];
 #pragma unroll
-  for (int c = 0; c < NCH; ++c)
-    if (kk[c] >= 0) atomicAdd(&hist[(kk[c] - mn) >> sh], 1);
+  for (int c = 0; c < E; ++c) {
+    const int p = 64 * c + lane;
+    ka[c] = K[p];
+    va[c] = Vt[p];
+    dg[c] = p < nc ? (ka[c] - mn) >> sh : 256;
+    atomicAdd(&hist[dg[c]], 1);
+  }
   wave_sync();
   {
     const int4 h = reinterpret_cast<int4*>(hist)[lane];
@@ -211,51 +221,160 @@ __device__ __forceinline__ void num_unit(const KArgs& a, unsigned char* base, in
     reinterpret_cast<int4*>(hist)[lane] = make_int4(ex, ex + h.x, ex + h.x + h.y, ex + h.x + h.y + h.z);
   }
   wave_sync();
-  // bucket scatter into K[0, c) (the table has been read into registers)
+  // scatter into buckets, B = [half, half + nc)
+  const int half = NCH * 32;
 #pragma unroll
-  for (int c = 0; c < NCH; ++c) {
-    if (kk[c] >= 0) {
-      const int p = atomicAdd(&hist[(kk[c] - mn) >> sh], 1);
-      K[p] = kk[c];
-      Vt[p] = vv[c];
-    }
+  for (int c = 0; c < E; ++c) {
+    const int pos = atomicAdd(&hist[dg[c]], 1);
+    const int dst = dg[c] < 256 ? half + pos : sink;
+    K[dst] = ka[c];
+    Vt[dst] = va[c];
   }
   wave_sync();
-  const int total = hist[255];
-  if (total != cnt) {
-    if (lane == 0) atomicOr(a.err, ERR_COUNT);
-    cnt = 0;  // write nothing for this unit
-  }
-  // rank inside the bucket, place into K[TS/2 + .]
-  const int half = TS / 2;
+  // rank inside the bucket (rows are unique), final order into A
 #pragma unroll
   for (int c = 0; c < E; ++c) {
     const int p = 64 * c + lane;
-    if (p < cnt) {
-      const int key = K[p];
-      const V val = Vt[p];
-      const int d = (key - mn) >> sh;
-      const int be = hist[d];
-      const int bs = d ? hist[d - 1] : 0;
-      int r = 0;
-      for (int q = bs; q < be; ++q) r += K[q] < key;
-      K[half + bs + r] = key;
-      Vt[half + bs + r] = val;
+    const bool ok = p < nc;
+    const int key = K[half + p];
+    const V val = Vt[half + p];
+    const int d = ok ? (key - mn) >> sh : 0;
+    const int be = ok ? hist[d] : 0;
+    const int bs = (ok && d) ? hist[d - 1] : 0;
+    // the first RANK_UNROLL members of the bucket without a loop, the rest in one
+    int r = 0;
+#pragma unroll
+    for (int q = 0; q < RANK_UNROLL; ++q) {
+      const int x = K[half + min(bs + q, NCH * 64 - 1)];
+      r += (bs + q < be && x < key) ? 1 : 0;
     }
+    if (ballot(be - bs > RANK_UNROLL) != 0)
+      for (int q = bs + RANK_UNROLL; q < be; ++q) r += K[half + q] < key;
+    const int dst = ok ? bs + r : sink;
+    K[dst] = key;
+    Vt[dst] = val;
   }
   wave_sync();
-  // unconditional stores (masked-off lanes write the dummy area) keep the number of
-  // memory operations per unit fixed, so the loads of the next unit stay in flight
-  // lanes past the end repeat the last entry's store (same address, same value);
-  // an empty unit writes into the dummy sink
+  // coalesced write-out; lanes past the end repeat the last entry's store (same
+  // address, same value); an empty unit writes into the dummy sink
   const long long dst = (long long)(a.out_r + o0), dsv = (long long)((V*)a.out_v + o0);
   const long long dmy = (long long)a.dummy + 2048 + 8LL * lane;  // write sink, never read
 #pragma unroll
   for (int c = 0; c < E; ++c) {
-    const int p = min(64 * c + lane, cnt - 1);
+    const int p = min(64 * c + lane, nc - 1);
     const int q = p < 0 ? 0 : p;
-    gstore<int>(cnt > 0 ? dst + 4LL * q : dmy, K[half + q]);
-    gstore<V>(cnt > 0 ? dsv + (long long)sizeof(V) * q : dmy, Vt[half + q]);
+    gstore<int>(nc > 0 ? dst + 4LL * q : dmy, K[q]);
+    gstore<V>(nc > 0 ? dsv + (long long)sizeof(V) * q : dmy, Vt[q]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Bitmap accumulator for dense columns: a row-indexed bitmap in LDS (the sparse
+// accumulator of Algorithm 4, with the dense array replaced by one bit per row and
+// the value array indexed by rank).  Symbolic: OR the rows in, count the bits.
+// Numeric: OR the rows in (the atomic OR's old word tells which entry came first),
+// prefix-popcount the bitmap, and use rank(row) = #set bits below it as the output
+// position.  That gives sorted output with no hash probing and no sort.  A first
+// entry stores its value; a later entry of the same row adds with compare-and-swap.
+// The bitmap holds bm_nq x 256 words (bm_nq x 8192 rows).
+// ---------------------------------------------------------------------------
+template <int E>
+__device__ __forceinline__ int bm_sym_unit(const KArgs& a, unsigned char* base, int u, const int (&rows)[E]) {
+  const int lane = lane_id();
+  uint4* bm4 = reinterpret_cast<uint4*>(base + a.off_bm);
+  unsigned* bm = reinterpret_cast<unsigned*>(bm4);
+  for (int q = 0; q < a.bm_nq; ++q) bm4[q * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
+  wave_sync();
+#pragma unroll
+  for (int t = 0; t < E; ++t)
+    if (lane + 64 * t < u) atomicOr(&bm[rows[t] >> 5], 1u << (rows[t] & 31));
+  wave_sync();
+  int c = 0;
+  for (int q = 0; q < a.bm_nq; ++q) {
+    const uint4 x = bm4[q * 64 + lane];
+    c += __popc(x.x) + __popc(x.y) + __popc(x.z) + __popc(x.w);
+  }
+  return wave_total_add(c);
+}
+
+template <int E, typename V>
+__device__ __forceinline__ void bm_num_unit(const KArgs& a, unsigned char* base, int u, int cnt, int o0,
+                                            const int (&rows)[E], const V (&vals)[E]) {
+  const int lane = lane_id();
+  uint4* bm4 = reinterpret_cast<uint4*>(base + a.off_bm);
+  unsigned* bm = reinterpret_cast<unsigned*>(bm4);
+  int* pre = reinterpret_cast<int*>(base + a.off_pre);
+  V* bv = reinterpret_cast<V*>(base + a.off_bvals);
+  const int nq = a.bm_nq;
+  for (int q = 0; q < nq; ++q) bm4[q * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
+  wave_sync();
+  bool first[E];
+#pragma unroll
+  for (int t = 0; t < E; ++t) {
+    first[t] = false;
+    if (lane + 64 * t < u) {
+      const unsigned bit = 1u << (rows[t] & 31);
+      const unsigned old = atomicOr(&bm[rows[t] >> 5], bit);
+      first[t] = (old & bit) == 0;
+    }
+  }
+  wave_sync();
+  // exclusive popcount prefix per group of 4 words; group g = q*64 + lane
+  int carry = 0;
+  for (int q = 0; q < nq; ++q) {
+    const uint4 x = bm4[q * 64 + lane];
+    const int n = __popc(x.x) + __popc(x.y) + __popc(x.z) + __popc(x.w);
+    const int incl = wave_scan_add(n);
+    pre[q * 64 + lane] = carry + incl - n;
+    carry += readlane(incl, 63);
+  }
+  int c = carry;
+  if (c != cnt) {
+    if (lane == 0) atomicOr(a.err, ERR_COUNT);
+    c = 0;
+  }
+  wave_sync();
+  int rk[E];
+#pragma unroll
+  for (int t = 0; t < E; ++t) {
+    const int r = lane + 64 * t < u ? rows[t] : 0;
+    const int w = r >> 5, g = w >> 2, wi = w & 3;
+    const uint4 x = bm4[g];
+    const int p = pre[g];
+    const unsigned word = wi == 0 ? x.x : wi == 1 ? x.y : wi == 2 ? x.z : x.w;
+    const int below = (wi > 0 ? __popc(x.x) : 0) + (wi > 1 ? __popc(x.y) : 0) + (wi > 2 ? __popc(x.z) : 0);
+    rk[t] = p + below + __popc(word & ((1u << (r & 31)) - 1u));
+  }
+#pragma unroll
+  for (int t = 0; t < E; ++t)
+    if (first[t]) bv[rk[t]] = vals[t];
+  wave_sync();
+#pragma unroll
+  for (int t = 0; t < E; ++t)
+    if (lane + 64 * t < u && !first[t]) lds_add_cas<V>(&bv[rk[t]], vals[t]);
+  wave_sync();
+  if (c == 0) return;
+  // rows of B(:,j) in ascending order: every lane emits the set bits of its groups
+  int* outr = a.out_r + o0;
+  for (int q = 0; q < nq; ++q) {
+    const int g = q * 64 + lane;
+    uint4 x = bm4[g];
+    int pos = pre[g];
+    const int rb = 128 * g;
+    while (x.x | x.y | x.z | x.w) {
+      int wi, b;
+      if (x.x) { wi = 0; b = __builtin_ctz(x.x); x.x &= x.x - 1; }
+      else if (x.y) { wi = 1; b = __builtin_ctz(x.y); x.y &= x.y - 1; }
+      else if (x.z) { wi = 2; b = __builtin_ctz(x.z); x.z &= x.z - 1; }
+      else { wi = 3; b = __builtin_ctz(x.w); x.w &= x.w - 1; }
+      outr[pos++] = rb + 32 * wi + b;
+    }
+  }
+  V* outv = (V*)a.out_v + o0;
+#pragma unroll
+  for (int t = 0; t < E; ++t) {
+    const int p = 64 * t + lane;
+    if (p < c) outv[p] = bv[p];
   }
 }
 
@@ -277,28 +396,34 @@ __device__ __forceinline__ void pipe_step(const KArgs& a, unsigned char* base, i
   const int lane = lane_id();
   {
     const int b = (t + 1) & 1;
-    int* P = (int*)(base + a.off_P) + 64 * b;
     long long* adj = (long long*)(base + a.off_adj) + 64 * b;
     long long* adjv = (long long*)(base + a.off_adjv) + 64 * b;
     nxt.j = t + 1 < nu ? readlane(ucol, (t + 1) & 63) : -1;
-    nxt.u = build_unit_meta<NUM, V>(a, rip, vap, ms, me, P, adj, adjv, nxt.j < 0);
+    nxt.u = build_unit_meta<E, NUM, V>(a, base, rip, vap, ms, me, adj, adjv, nxt.j < 0);
     if (NUM) {
       nxt.o0 = readlane(mc, 0);
       nxt.cnt = nxt.j < 0 ? 0 : readlane(mc, 1) - nxt.o0;
     }
     issue_meta_loads<NUM>(a, cpp, t + 2 < nu ? readlane(ucol, (t + 2) & 63) : -1, ms, me, mc);
     wave_sync();
-    issue_unit_loads<E, NUM, V>(a, P, adj, adjv, nxt.u, nxt.rows, nxt.vals);
+    issue_unit_loads<E, NUM, V>(a, base, adj, adjv, nxt.u, nxt.rows, nxt.vals);
   }
-  if (NUM) {
+  if (NUM && a.bm_nq > 0) {
+    bm_num_unit<E, V>(a, base, cur.u, cur.cnt, cur.o0, cur.rows, cur.vals);
+  } else if (NUM) {
     num_unit<E, V>(a, base, cur.u, cur.cnt, cur.o0, cur.rows, cur.vals);
+  } else if (a.bm_nq > 0) {
+    const int cnt = bm_sym_unit<E>(a, base, cur.u, cur.rows);
+    const long long dst = cur.j >= 0 ? (long long)(a.colcnt + cur.j) : (long long)a.dummy + 2048 + 8LL * lane;
+    if (lane == 0) gstore<int>(dst, cnt);
+    wave_sync();
   } else {
     int* T = (int*)base;
     int TS = slots_for(cur.u, a.alpha_q);
     if (TS > a.ts_max) TS = a.ts_max;
     for (int s = lane; s < TS; s += 64) T[s] = -1;
     wave_sync();
-    const int newc = sym_insert_batch<E>(T, TS, a.hash_mode, cur.u, cur.rows, a.err);
+    const int newc = insert_batch<E, false, V>(T, nullptr, TS, a.hash_mode, cur.u, cur.rows, cur.vals, a.err);
     const int cnt = wave_total_add(newc);
     const long long dst = cur.j >= 0 ? (long long)(a.colcnt + cur.j) : (long long)a.dummy + 2048 + 8LL * lane;
     if (lane == 0) gstore<int>(dst, cnt);
@@ -326,10 +451,9 @@ __global__ __launch_bounds__(256) void k_wave_pipe(KArgs a, const int* __restric
   // prologue: metadata and entry loads of unit 0, pointers of unit 1
   issue_meta_loads<NUM>(a, cpp, readlane(ucol, 0), ms, me, mc);
   {
-    int* P = (int*)(base + a.off_P);
     long long* adj = (long long*)(base + a.off_adj);
     long long* adjv = (long long*)(base + a.off_adjv);
-    A.u = build_unit_meta<NUM, V>(a, rip, vap, ms, me, P, adj, adjv, false);
+    A.u = build_unit_meta<E, NUM, V>(a, base, rip, vap, ms, me, adj, adjv, false);
     A.j = readlane(ucol, 0);
     if (NUM) {
       A.o0 = readlane(mc, 0);
@@ -337,7 +461,7 @@ __global__ __launch_bounds__(256) void k_wave_pipe(KArgs a, const int* __restric
     }
     issue_meta_loads<NUM>(a, cpp, nu > 1 ? readlane(ucol, 1) : -1, ms, me, mc);
     wave_sync();
-    issue_unit_loads<E, NUM, V>(a, P, adj, adjv, A.u, A.rows, A.vals);
+    issue_unit_loads<E, NUM, V>(a, base, adj, adjv, A.u, A.rows, A.vals);
   }
   const int steps = (nu + 1) & ~1;
   for (int t = 0; t < steps; t += 2) {
@@ -349,21 +473,32 @@ __global__ __launch_bounds__(256) void k_wave_pipe(KArgs a, const int* __restric
 // ---- host side ----
 bool wave_pipe_ok(int k, int alpha_num_q) { return k <= 64 && alpha_num_q == 512; }
 
-void lds_layout_pipe(int bin, bool numeric, int vbytes, int ts_max, KArgs& a) {
-  int off = ts_max * 4;
-  if (numeric) off += ts_max * vbytes;
+void lds_layout_pipe(int bin, bool numeric, int vbytes, int ts_max, int bm_nq, KArgs& a) {
+  const int E = wave_bin_E(bin);
+  // region 1: hash table (keys + 64 sink slots, values) or bitmap (+ group prefix, values)
+  int hash_bytes = (ts_max + 64) * 4;
+  if (numeric) hash_bytes += (ts_max + 64) * vbytes + 272 * 4;
+  int bm_bytes = 0;
+  a.bm_nq = bm_nq;
+  if (bm_nq > 0) {
+    a.off_bm = 0;
+    a.off_pre = bm_nq * 256 * 4;
+    a.off_bvals = a.off_pre + bm_nq * 64 * 4;
+    bm_bytes = numeric ? a.off_bvals + 64 * E * vbytes : a.off_pre;
+  }
+  int off = bm_nq > 0 ? bm_bytes : hash_bytes;
   off = (off + 15) & ~15;
-  a.off_hist = off;
-  if (numeric) off += 256 * 4;
+  a.off_hist = ((ts_max + 64) * 4 + (ts_max + 64) * vbytes + 15) & ~15;  // used by the hash layout only
+  a.off_mark = off;
+  off += 64 * E;
+  off = (off + 15) & ~15;
   a.off_P = off;
-  off += 2 * 64 * 4;
   a.off_adj = off;
   off += 2 * 64 * 8;
   a.off_adjv = off;
   if (numeric) off += 2 * 64 * 8;
   a.slice_bytes = (off + 15) & ~15;
   a.ts_max = ts_max;
-  (void)bin;
 }
 
 template <bool NUM, typename V>

@@ -100,6 +100,21 @@ def test_sliding_windows_match_plain():
     assert np.array_equal(plain[2], slid[2])
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("shape", [(65536, 1500, 32, 16.0), (10000, 800, 8, 40.0), (1, 300, 5, 0.5),
+                                   (131072, 300, 16, 30.0), (777, 500, 64, 6.0)])
+def test_accum_modes(mode, shape):
+    """Hash tables and the bitmap accumulator give the same result (wave bins)."""
+    m, n, k, d = shape
+    note(f"accum_mode={mode} m={m} n={n} k={k} d={d}")
+    for values in ("int32f", "int64f"):
+        batch = workloads.er(m, n, k, d, seed=m + k, values=values)
+        got = run_gpu(batch, _opts(accum_mode=mode))
+        assert_matches(batch, got, oracle.spkadd(batch), exact_values=True)
+    batch = workloads.er(m, n, k, d, seed=m + k + 1, values="f32")
+    assert_matches(batch, run_gpu(batch, _opts(accum_mode=mode, bitmap_ratio=4.0)), oracle.spkadd(batch))
+
+
 def test_degenerate_hash():
     note("degenerate_hash")
     batch = workloads.er(3000, 200, 5, 30.0, seed=8, values="int32f")
