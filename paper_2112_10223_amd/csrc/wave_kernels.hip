@@ -354,27 +354,46 @@ __device__ __forceinline__ void bm_num_unit(const KArgs& a, unsigned char* base,
     if (lane + 64 * t < u && !first[t]) lds_add_cas<V>(&bv[rk[t]], vals[t]);
   wave_sync();
   if (c == 0) return;
-  // rows of B(:,j) in ascending order: every lane emits the set bits of its groups
-  int* outr = a.out_r + o0;
+  // rows of B(:,j) in ascending order, one coalesced chunk of 64 positions at a time:
+  // every non-empty group g marks output position pre[g] with g; a running max-scan
+  // over the marks gives the group of each position, and the row is the
+  // (p - pre[g])-th set bit of that group.
+  int* gmark = reinterpret_cast<int*>(base + a.off_mark2);
+  for (int q = lane; q < 16 * E; q += 64) reinterpret_cast<int4*>(gmark)[q] = make_int4(-1, -1, -1, -1);
+  wave_sync();
   for (int q = 0; q < nq; ++q) {
     const int g = q * 64 + lane;
-    uint4 x = bm4[g];
-    int pos = pre[g];
-    const int rb = 128 * g;
-    while (x.x | x.y | x.z | x.w) {
-      int wi, b;
-      if (x.x) { wi = 0; b = __builtin_ctz(x.x); x.x &= x.x - 1; }
-      else if (x.y) { wi = 1; b = __builtin_ctz(x.y); x.y &= x.y - 1; }
-      else if (x.z) { wi = 2; b = __builtin_ctz(x.z); x.z &= x.z - 1; }
-      else { wi = 3; b = __builtin_ctz(x.w); x.w &= x.w - 1; }
-      outr[pos++] = rb + 32 * wi + b;
-    }
+    const uint4 x = bm4[g];
+    if ((x.x | x.y | x.z | x.w) != 0u) gmark[pre[g]] = g;
   }
+  wave_sync();
+  int* outr = a.out_r + o0;
   V* outv = (V*)a.out_v + o0;
+  int gcarry = 0;
 #pragma unroll
   for (int t = 0; t < E; ++t) {
     const int p = 64 * t + lane;
-    if (p < c) outv[p] = bv[p];
+    const int g = max(wave_scan_max(gmark[p]), gcarry);
+    gcarry = readlane(g, 63);
+    if (p < c) {
+      const uint4 x = bm4[g];
+      int kth = p - pre[g];
+      const int c0 = __popc(x.x), c1 = __popc(x.y), c2 = __popc(x.z);
+      int wi = 0;
+      unsigned w = x.x;
+      if (kth >= c0) { kth -= c0; wi = 1; w = x.y;
+        if (kth >= c1) { kth -= c1; wi = 2; w = x.z;
+          if (kth >= c2) { kth -= c2; wi = 3; w = x.w; } } }
+      // position of the kth set bit of w (binary search on popcounts of the low halves)
+      int pos = 0, cc;
+      cc = __popc(w & 0xffffu); if (kth >= cc) { kth -= cc; pos += 16; w >>= 16; }
+      cc = __popc(w & 0xffu);   if (kth >= cc) { kth -= cc; pos += 8;  w >>= 8; }
+      cc = __popc(w & 0xfu);    if (kth >= cc) { kth -= cc; pos += 4;  w >>= 4; }
+      cc = __popc(w & 0x3u);    if (kth >= cc) { kth -= cc; pos += 2;  w >>= 2; }
+      cc = (int)(w & 1u);       if (kth >= cc) { pos += 1; }
+      outr[p] = 128 * g + 32 * wi + pos;
+      outv[p] = bv[p];
+    }
   }
 }
 
@@ -484,7 +503,8 @@ void lds_layout_pipe(int bin, bool numeric, int vbytes, int ts_max, int bm_nq, K
     a.off_bm = 0;
     a.off_pre = bm_nq * 256 * 4;
     a.off_bvals = a.off_pre + bm_nq * 64 * 4;
-    bm_bytes = numeric ? a.off_bvals + 64 * E * vbytes : a.off_pre;
+    a.off_mark2 = a.off_bvals + 64 * E * vbytes;
+    bm_bytes = numeric ? a.off_mark2 + 64 * E * 4 : a.off_pre;
   }
   int off = bm_nq > 0 ? bm_bytes : hash_bytes;
   off = (off + 15) & ~15;
