@@ -86,7 +86,7 @@ struct KArgs {
   int ts_max;             // table slots available
   int off_P, off_adj, off_adjv, off_hist, off_match, off_mark, slice_bytes;
   int bm_nq;              // wave bitmap mode: bitmap rows of 256 words (0 = hash mode)
-  int off_bm, off_pre, off_bvals, off_mark2;
+  int off_bm, off_pre, off_bvals, off_brows;
 };
 
 // ---- plan kernels (plan_kernels.hip) ----

@@ -275,7 +275,8 @@ __device__ __forceinline__ void num_unit(const KArgs& a, unsigned char* base, in
 // Numeric: OR the rows in (the atomic OR's old word tells which entry came first),
 // prefix-popcount the bitmap, and use rank(row) = #set bits below it as the output
 // position.  That gives sorted output with no hash probing and no sort.  A first
-// entry stores its value; a later entry of the same row adds with compare-and-swap.
+// entry stores its row and value at that position; a later entry of the same row
+// adds with compare-and-swap.
 // The bitmap holds bm_nq x 256 words (bm_nq x 8192 rows).
 // ---------------------------------------------------------------------------
 template <int E>
@@ -303,8 +304,9 @@ __device__ __forceinline__ void bm_num_unit(const KArgs& a, unsigned char* base,
   const int lane = lane_id();
   uint4* bm4 = reinterpret_cast<uint4*>(base + a.off_bm);
   unsigned* bm = reinterpret_cast<unsigned*>(bm4);
-  int* pre = reinterpret_cast<int*>(base + a.off_pre);
+  unsigned short* pw = reinterpret_cast<unsigned short*>(base + a.off_pre);  // set bits below each word
   V* bv = reinterpret_cast<V*>(base + a.off_bvals);
+  int* br = reinterpret_cast<int*>(base + a.off_brows);
   const int nq = a.bm_nq;
   for (int q = 0; q < nq; ++q) bm4[q * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
   wave_sync();
@@ -319,14 +321,18 @@ __device__ __forceinline__ void bm_num_unit(const KArgs& a, unsigned char* base,
     }
   }
   wave_sync();
-  // exclusive popcount prefix per group of 4 words; group g = q*64 + lane
+  // exclusive popcount prefix per word (ranks stay below 64 E <= 1024, so 16 bits
+  // hold them); lane handles the 4 words of group q*64 + lane
   int carry = 0;
   for (int q = 0; q < nq; ++q) {
     const uint4 x = bm4[q * 64 + lane];
-    const int n = __popc(x.x) + __popc(x.y) + __popc(x.z) + __popc(x.w);
+    const int c0 = __popc(x.x), c1 = __popc(x.y), c2 = __popc(x.z), c3 = __popc(x.w);
+    const int n = c0 + c1 + c2 + c3;
     const int incl = wave_scan_add(n);
-    pre[q * 64 + lane] = carry + incl - n;
+    const int p0 = carry + incl - n, p1 = p0 + c0, p2 = p1 + c1, p3 = p2 + c2;
     carry += readlane(incl, 63);
+    reinterpret_cast<uint2*>(pw)[q * 64 + lane] =
+        make_uint2((unsigned)p0 | ((unsigned)p1 << 16), (unsigned)p2 | ((unsigned)p3 << 16));
   }
   int c = carry;
   if (c != cnt) {
@@ -334,66 +340,36 @@ __device__ __forceinline__ void bm_num_unit(const KArgs& a, unsigned char* base,
     c = 0;
   }
   wave_sync();
+  // rank(row) = set bits below it = output position; the first entry of a row puts
+  // the row and its value there, later entries of the row add their values
   int rk[E];
 #pragma unroll
   for (int t = 0; t < E; ++t) {
     const int r = lane + 64 * t < u ? rows[t] : 0;
-    const int w = r >> 5, g = w >> 2, wi = w & 3;
-    const uint4 x = bm4[g];
-    const int p = pre[g];
-    const unsigned word = wi == 0 ? x.x : wi == 1 ? x.y : wi == 2 ? x.z : x.w;
-    const int below = (wi > 0 ? __popc(x.x) : 0) + (wi > 1 ? __popc(x.y) : 0) + (wi > 2 ? __popc(x.z) : 0);
-    rk[t] = p + below + __popc(word & ((1u << (r & 31)) - 1u));
+    const int w = r >> 5;
+    rk[t] = (int)pw[w] + __popc(bm[w] & ((1u << (r & 31)) - 1u));
   }
 #pragma unroll
   for (int t = 0; t < E; ++t)
-    if (first[t]) bv[rk[t]] = vals[t];
+    if (first[t]) {
+      bv[rk[t]] = vals[t];
+      br[rk[t]] = rows[t];
+    }
   wave_sync();
 #pragma unroll
   for (int t = 0; t < E; ++t)
     if (lane + 64 * t < u && !first[t]) lds_add_cas<V>(&bv[rk[t]], vals[t]);
   wave_sync();
-  if (c == 0) return;
-  // rows of B(:,j) in ascending order, one coalesced chunk of 64 positions at a time:
-  // every non-empty group g marks output position pre[g] with g; a running max-scan
-  // over the marks gives the group of each position, and the row is the
-  // (p - pre[g])-th set bit of that group.
-  int* gmark = reinterpret_cast<int*>(base + a.off_mark2);
-  for (int q = lane; q < 16 * E; q += 64) reinterpret_cast<int4*>(gmark)[q] = make_int4(-1, -1, -1, -1);
-  wave_sync();
-  for (int q = 0; q < nq; ++q) {
-    const int g = q * 64 + lane;
-    const uint4 x = bm4[g];
-    if ((x.x | x.y | x.z | x.w) != 0u) gmark[pre[g]] = g;
-  }
-  wave_sync();
-  int* outr = a.out_r + o0;
-  V* outv = (V*)a.out_v + o0;
-  int gcarry = 0;
+  // coalesced write-out of B(:,j), rows ascending; lanes past the end repeat the last
+  // entry's store, and an empty (or failed) unit writes into the dummy sink
+  const long long dst = (long long)(a.out_r + o0), dsv = (long long)((V*)a.out_v + o0);
+  const long long dmy = (long long)a.dummy + 2048 + 8LL * lane;
 #pragma unroll
   for (int t = 0; t < E; ++t) {
-    const int p = 64 * t + lane;
-    const int g = max(wave_scan_max(gmark[p]), gcarry);
-    gcarry = readlane(g, 63);
-    if (p < c) {
-      const uint4 x = bm4[g];
-      int kth = p - pre[g];
-      const int c0 = __popc(x.x), c1 = __popc(x.y), c2 = __popc(x.z);
-      int wi = 0;
-      unsigned w = x.x;
-      if (kth >= c0) { kth -= c0; wi = 1; w = x.y;
-        if (kth >= c1) { kth -= c1; wi = 2; w = x.z;
-          if (kth >= c2) { kth -= c2; wi = 3; w = x.w; } } }
-      // position of the kth set bit of w (binary search on popcounts of the low halves)
-      int pos = 0, cc;
-      cc = __popc(w & 0xffffu); if (kth >= cc) { kth -= cc; pos += 16; w >>= 16; }
-      cc = __popc(w & 0xffu);   if (kth >= cc) { kth -= cc; pos += 8;  w >>= 8; }
-      cc = __popc(w & 0xfu);    if (kth >= cc) { kth -= cc; pos += 4;  w >>= 4; }
-      cc = __popc(w & 0x3u);    if (kth >= cc) { kth -= cc; pos += 2;  w >>= 2; }
-      cc = (int)(w & 1u);       if (kth >= cc) { pos += 1; }
-      outr[p] = 128 * g + 32 * wi + pos;
-      outv[p] = bv[p];
-    }
+    const int p = min(64 * t + lane, c - 1);
+    const int q = p < 0 ? 0 : p;
+    gstore<int>(c > 0 ? dst + 4LL * q : dmy, br[q]);
+    gstore<V>(c > 0 ? dsv + (long long)sizeof(V) * q : dmy, bv[q]);
   }
 }
 
@@ -502,9 +478,9 @@ void lds_layout_pipe(int bin, bool numeric, int vbytes, int ts_max, int bm_nq, K
   if (bm_nq > 0) {
     a.off_bm = 0;
     a.off_pre = bm_nq * 256 * 4;
-    a.off_bvals = a.off_pre + bm_nq * 64 * 4;
-    a.off_mark2 = a.off_bvals + 64 * E * vbytes;
-    bm_bytes = numeric ? a.off_mark2 + 64 * E * 4 : a.off_pre;
+    a.off_bvals = a.off_pre + bm_nq * 256 * 2;
+    a.off_brows = a.off_bvals + 64 * E * vbytes;
+    bm_bytes = numeric ? a.off_brows + 64 * E * 4 : a.off_pre;
   }
   int off = bm_nq > 0 ? bm_bytes : hash_bytes;
   off = (off + 15) & ~15;
