@@ -64,7 +64,7 @@ def kernel_of_column(u: np.ndarray, cap: int, wave_max: int = 1024) -> np.ndarra
 
 def source_sha() -> str:
     h = hashlib.sha256()
-    for fn in ("hash_kernels.hip", "device.h", "internal.h"):
+    for fn in ("hash_kernels.hip", "wave_kernels.hip", "hash_common.h", "device.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_2112_10223_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -115,6 +115,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-trace", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--trace-steps", type=int, default=3, help="untimed steps with every launch traced")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the SpKAdd path here is single-GPU.",
@@ -140,7 +141,10 @@ def main() -> int:
     ris = [torch.from_numpy(r).to(dev) for r in batch.rowidx]
     vas = [torch.from_numpy(v).to(dev) for v in batch.vals]
     dtype = binding.SPKADD_F64 if f64 else binding.SPKADD_F32
-    opts = binding.make_opts(flags=0 if args.no_trace else binding.SPKADD_FLAG_TRACE)
+    # timed steps record HIP events around the numeric launches only (the dominant
+    # kernels); a separate untimed pass traces every launch for the phase breakdown
+    opts = binding.make_opts(flags=0 if args.no_trace else binding.SPKADD_FLAG_TRACE_NUMERIC)
+    opts_all = binding.make_opts(flags=binding.SPKADD_FLAG_TRACE)
 
     # output sizes: one untimed call
     plan = binding.spkadd_plan(m, n, cps, ris, dtype, opts)
@@ -152,47 +156,74 @@ def main() -> int:
     vals_c = torch.empty(max(nnz_out, 1), dtype=vas[0].dtype, device=dev)
     nnz_in = batch.nnz_in
 
-    def step():
-        p = binding.spkadd_plan(m, n, cps, ris, dtype, opts)
-        binding.spkadd_symbolic(p, colptr_c)
-        binding.spkadd_numeric(p, vas, rowidx_c, vals_c)
+    # pointer arrays and the stream handle are marshalled once; every step still
+    # runs the whole path on the device
+    pcp, pri, pva = binding.PtrArray(cps), binding.PtrArray(ris), binding.PtrArray(vas, non_null=True)
+    stream = binding._stream_ptr(None)
+
+    host_s = {"plan": 0.0, "symbolic": 0.0, "numeric": 0.0}
+
+    def step(o):
+        t_a = time.perf_counter()
+        p = binding.spkadd_plan(m, n, pcp, pri, dtype, o, stream)
+        t_b = time.perf_counter()
+        binding.spkadd_symbolic(p, colptr_c, stream)
+        t_c = time.perf_counter()
+        binding.spkadd_numeric(p, pva, rowidx_c, vals_c, stream)
+        t_d = time.perf_counter()
+        host_s["plan"] += t_b - t_a
+        host_s["symbolic"] += t_c - t_b
+        host_s["numeric"] += t_d - t_c
         return p
 
-    prev = None
-    for _ in range(args.warmup):
-        p = step()
-        if prev is not None:
-            binding.spkadd_trace(prev)
-            prev.free()
-        prev = p
+    def run(nsteps, o, collect):
+        """nsteps steps; a plan is freed (after reading its trace) once the next one is
+        queued, so no step waits for the previous one to drain."""
+        prev, traces = None, []
+        for _ in range(nsteps):
+            p = step(o)
+            if prev is not None:
+                if collect:
+                    traces.append(binding.spkadd_trace(prev))
+                prev.free()
+            prev = p
+        return prev, traces
+
+    last, _ = run(args.warmup, opts, False)
+    if last is not None:
+        last.free()
     torch.cuda.synchronize()
-    traces = []
+    for kk in host_s:
+        host_s[kk] = 0.0
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        p = step()
-        if prev is not None:
-            if traces is not None and prev is not None:
-                tr = binding.spkadd_trace(prev)
-                traces.append(tr)
-            prev.free()
-        prev = p
+    last, traces = run(args.steps, opts, not args.no_trace)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    traces.append(binding.spkadd_trace(prev))
-    prev.free()
-    traces = traces[1:]  # the first record belongs to the last warm-up step
+    if not args.no_trace:
+        traces.append(binding.spkadd_trace(last))
+    last.free()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    host_call_ms = {kk: round(v * 1e3 / args.steps, 4) for kk, v in host_s.items()}
 
-    # per-kernel mean launch time over the timed steps
-    per_kernel = {}
-    for tr in traces:
-        for name, ms in tr:
-            per_kernel.setdefault(name, []).append(ms)
-    mean_ms = {kname: float(np.mean(v)) for kname, v in per_kernel.items()}
+    def mean_by_kernel(trs):
+        per = {}
+        for tr in trs:
+            for name, ms in tr:
+                per.setdefault(name, []).append(ms)
+        return {kname: float(np.mean(v)) for kname, v in per.items()}
+
+    mean_ms = mean_by_kernel(traces)  # numeric launches of the timed steps
+    # phase breakdown: a few more steps with every launch traced (not timed)
+    last, tr_all = run(args.trace_steps, opts_all, True)
+    if last is not None:
+        tr_all.append(binding.spkadd_trace(last))
+        last.free()
+    torch.cuda.synchronize()
+    all_ms = mean_by_kernel(tr_all)
     phase_ms = {"plan": 0.0, "symbolic": 0.0, "numeric": 0.0}
-    for kname, ms in mean_ms.items():
-        ph = "numeric" if kname.startswith("num_") else "symbolic" if kname.startswith(("sym_", "scan", "win_colsum")) \
-            else "plan"
+    for kname, ms in all_ms.items():
+        ph = "numeric" if kname.startswith(("num_", "put_ptrs_num")) else \
+            "symbolic" if kname.startswith(("sym_", "scan", "win_colsum")) else "plan"
         phase_ms[ph] += ms
 
     # algorithmic bytes of the numeric kernels, per launch
@@ -204,6 +235,9 @@ def main() -> int:
     kern = kernel_of_column(u, cap)
     roofline = None
     num_kernels = [kname for kname in mean_ms if kname.startswith("num_")]
+    if not num_kernels:  # timed without events: fall back to the traced pass
+        mean_ms = all_ms
+        num_kernels = [kname for kname in mean_ms if kname.startswith("num_")]
     if num_kernels:
         dom = max(num_kernels, key=lambda x: mean_ms[x])
         sel = kern == dom
@@ -235,7 +269,8 @@ def main() -> int:
         "hbm_gbps_alg_step": round(b_alg / (ms_per_step * 1e-3) / 1e9, 1),
         "hbm_frac_alg_step": round(b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "phase_ms": {kk: round(v, 4) for kk, v in phase_ms.items()},
-        "kernel_ms": {kk: round(v, 5) for kk, v in sorted(mean_ms.items())},
+        "host_call_ms": host_call_ms,
+        "kernel_ms": {kk: round(v, 5) for kk, v in sorted(all_ms.items())},
         "bins": {kk: stats[kk] for kk in ("n_wave_cols", "n_wg_cols", "n_window_cols", "n_windows")},
         "roofline": roofline,
         "cpu_baseline": None,

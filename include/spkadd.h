@@ -63,6 +63,7 @@ typedef enum spkadd_dtype { SPKADD_F32 = 0, SPKADD_F64 = 1 } spkadd_dtype;
 /* opts.flags */
 #define SPKADD_FLAG_VALIDATE 1u /* check every input on the device in spkadd_plan */
 #define SPKADD_FLAG_TRACE 2u    /* time every kernel launch with HIP events */
+#define SPKADD_FLAG_TRACE_NUMERIC 4u /* time only the launches of spkadd_numeric */
 
 /* opts.force_bin: test hook that routes columns to one accumulator family */
 #define SPKADD_BIN_AUTO (-1)
@@ -111,8 +112,8 @@ void spkadd_opts_default(spkadd_opts* opts);
  *   rowidx : HOST array of k DEVICE pointers, each int32[colptr_i[n]].
  *   dtype  : value type of the later spkadd_numeric calls.
  *   opts   : NULL for defaults.
- *   stream : HIP stream for all device work.  This call waits on the stream once,
- *            to size the window tables.
+ *   stream : HIP stream for all device work.  This call waits once for the bin
+ *            counts, and a few more times when some columns need row windows.
  * Errors: INVALID (null pointers, k < 1, negative sizes, bad option values, or
  * malformed inputs when SPKADD_FLAG_VALIDATE is set), OVERFLOW (some u_j above
  * INT32_MAX), OOM, HIP.
@@ -139,11 +140,13 @@ spkadd_status spkadd_symbolic(spkadd_plan_t plan, int32_t* colptr_c, int64_t* nn
  * chip and written to rowidx_c / values_c at colptr(B).
  *   values   : HOST array of k DEVICE pointers to the input values (float or double
  *              as the plan's dtype), aligned with the rowidx arrays given to spkadd_plan.
+ *              Every pointer must be non-NULL unless all inputs are empty; the pointer
+ *              of an input without entries is never read through.
  *   rowidx_c : DEVICE int32[nnz(B)].
  *   values_c : DEVICE float[nnz(B)] or double[nnz(B)].
  * The call is asynchronous on `stream`.  It may be repeated with new values for
  * the same patterns.
- * Errors: STATE (spkadd_symbolic not yet run), INVALID, HIP.
+ * Errors: STATE (spkadd_symbolic not yet run), INVALID (NULL arguments), HIP.
  */
 spkadd_status spkadd_numeric(spkadd_plan_t plan, const void* const* values, int32_t* rowidx_c, void* values_c,
                              hipStream_t stream);
@@ -173,8 +176,8 @@ typedef struct spkadd_stats {
 } spkadd_stats;
 spkadd_status spkadd_get_stats(spkadd_plan_t plan, spkadd_stats* out);
 
-/* Kernel timings recorded under SPKADD_FLAG_TRACE by the last plan / symbolic /
- * numeric calls of this plan.  spkadd_trace_count gives how many launches were
+/* Kernel timings recorded under SPKADD_FLAG_TRACE (or SPKADD_FLAG_TRACE_NUMERIC) by the
+ * last plan / symbolic / numeric calls of this plan.  spkadd_trace_count gives how many launches were
  * recorded.  spkadd_trace_get copies the kernel name of launch idx (NUL-terminated,
  * at most name_cap bytes) and its elapsed milliseconds.  It waits for the events to
  * complete. */

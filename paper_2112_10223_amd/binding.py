@@ -17,7 +17,7 @@ SPKADD_OK, SPKADD_ERR_INVALID, SPKADD_ERR_OOM, SPKADD_ERR_HIP, SPKADD_ERR_STATE,
     SPKADD_ERR_UNSUPPORTED = range(7)
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OOM", 3: "HIP", 4: "STATE", 5: "OVERFLOW", 6: "UNSUPPORTED"}
 SPKADD_F32, SPKADD_F64 = 0, 1
-SPKADD_FLAG_VALIDATE, SPKADD_FLAG_TRACE = 1, 2
+SPKADD_FLAG_VALIDATE, SPKADD_FLAG_TRACE, SPKADD_FLAG_TRACE_NUMERIC = 1, 2, 4
 SPKADD_BIN_AUTO, SPKADD_BIN_WAVE, SPKADD_BIN_WG, SPKADD_BIN_WINDOW = -1, 0, 1, 2
 SPKADD_ACCUM_AUTO, SPKADD_ACCUM_HASH, SPKADD_ACCUM_BITMAP = 0, 1, 2
 
@@ -96,14 +96,36 @@ def _check(status: int):
 
 
 def _stream_ptr(stream):
+    if isinstance(stream, ctypes.c_void_p):
+        return stream
     if stream is None:
         import torch
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
 
 
-def _ptr_array(tensors):
-    return (ctypes.c_void_p * len(tensors))(*[t.data_ptr() if t is not None else 0 for t in tensors])
+class PtrArray:
+    """A host array of device pointers built once from k tensors, for callers that
+    pass the same inputs many times.  Keeps the tensors alive.  With
+    non_null=True, pointers of empty tensors (which torch reports as 0) are replaced
+    by another input's pointer; they are never read through."""
+
+    def __init__(self, tensors, non_null: bool = False):
+        self.tensors = list(tensors)
+        ptrs = [t.data_ptr() if t is not None else 0 for t in self.tensors]
+        if non_null:
+            fill = next((q for q in ptrs if q), 0)
+            ptrs = [q or fill for q in ptrs]
+        self.arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
+
+    def __len__(self):
+        return len(self.tensors)
+
+
+def _ptr_array(tensors, non_null: bool = False):
+    if isinstance(tensors, PtrArray):
+        return tensors.arr
+    return PtrArray(tensors, non_null).arr
 
 
 def make_opts(**kw) -> Opts:
@@ -136,7 +158,9 @@ class Plan:
 
 
 def spkadd_plan(m, n, colptrs, rowidxs, dtype=SPKADD_F32, opts: Opts | None = None, stream=None) -> Plan:
-    """colptrs / rowidxs: k int32 device tensors each (torch)."""
+    """colptrs / rowidxs: k int32 device tensors each (torch), or PtrArray objects.
+    stream: a torch stream, a raw hipStream_t (int or ctypes.c_void_p), or None for
+    torch's current stream."""
     k = len(colptrs)
     h = ctypes.c_void_p()
     cp = _ptr_array(colptrs)
@@ -155,7 +179,7 @@ def spkadd_symbolic(plan: Plan, colptr_c, stream=None) -> int:
 
 
 def spkadd_numeric(plan: Plan, values, rowidx_c, values_c, stream=None) -> None:
-    va = _ptr_array(values)
+    va = _ptr_array(values, non_null=True)
     _check(lib().spkadd_numeric(plan.handle, ctypes.cast(va, ctypes.c_void_p),
                                 rowidx_c.data_ptr() if rowidx_c is not None else None,
                                 values_c.data_ptr() if values_c is not None else None, _stream_ptr(stream)))

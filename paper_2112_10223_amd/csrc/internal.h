@@ -49,9 +49,10 @@ struct PlanParams {
   float win_fill;   // target window input count = cap_in * win_fill
 };
 
-// Summary written by the plan kernels and copied to the host once.
+// Summary written by the plan kernels; the host reads it from a pinned slot.
 struct PlanSummary {
   unsigned long long nnz_in;
+  long long total;   // result of the last scan (nnz(B), or the refined window count)
   int err;
   int bin_count[NBINS];
   int n_windows;
@@ -90,8 +91,17 @@ struct KArgs {
 };
 
 // ---- plan kernels (plan_kernels.hip) ----
-void launch_bounds(const PlanParams& p, const int* const* d_cp, int* d_u, unsigned char* d_bin, int* d_colcnt,
-                   int* d_hist, PlanSummary* d_sum, hipStream_t s);
+// Device pointers passed by value (kernel arguments) to k_put_ptrs.
+struct PtrChunk {
+  static constexpr int kMax = 128;
+  const void* p[kMax];
+  int count;
+};
+
+void launch_put_ptrs(const void* const* host_ptrs, int count, const void** d_dst, PlanSummary* d_sum,
+                     void* d_dummy, hipStream_t s);
+void launch_bounds(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int* d_u,
+                   unsigned char* d_bin, int* d_colcnt, int* d_hist, PlanSummary* d_sum, hipStream_t s);
 void launch_validate(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, PlanSummary* d_sum,
                      hipStream_t s);
 void launch_bin_scan(int nblk, int* d_hist, int* d_binoff, PlanSummary* d_sum, hipStream_t s);
@@ -99,8 +109,6 @@ void launch_bin_scatter(const PlanParams& p, const unsigned char* d_bin, const i
                         int* d_list, hipStream_t s);
 void launch_win_scan(const PlanParams& p, const int* d_list, const int* d_binoff, const int* d_u, int* d_wfirst,
                      PlanSummary* d_sum, hipStream_t s);
-void launch_check_ptrs(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, PlanSummary* d_sum,
-                       hipStream_t s);
 void launch_win_fill(const PlanParams& p, int n_wcols, const int* d_wfirst, int* d_win_c, int* d_brow, int* d_bcol,
                      hipStream_t s);
 void launch_win_search(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,

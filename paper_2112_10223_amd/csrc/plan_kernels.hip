@@ -26,11 +26,14 @@ __device__ __forceinline__ int classify(long long u, const PlanParams& p) {
 
 // u_j = sum_i nnz(A_i(:,j)), bin of j, per-block bin histogram, nnz_in.
 __global__ __launch_bounds__(PLAN_THREADS) void k_bounds(PlanParams p, const int* const* __restrict__ cp,
-                                                         int* __restrict__ u, unsigned char* __restrict__ bin,
+                                                         const int* const* __restrict__ ri, int* __restrict__ u, unsigned char* __restrict__ bin,
                                                          int* __restrict__ colcnt, int* __restrict__ hist,
                                                          PlanSummary* __restrict__ sum) {
   __shared__ int wh[PLAN_THREADS / 64][NBINS];
   __shared__ unsigned long long red[PLAN_THREADS / 64 + 1];
+  if (blockIdx.x == 0)  // an input with entries must come with a row array
+    for (int i = threadIdx.x; i < p.k; i += PLAN_THREADS)
+      if (cp[i][p.n] > 0 && ri[i] == nullptr) atomicOr(&sum->err, ERR_INPUT);
   const int j = blockIdx.x * PLAN_THREADS + threadIdx.x;
   const int lane = lane_id(), w = threadIdx.x >> 6;
   long long uj = 0;
@@ -89,39 +92,43 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_validate(PlanParams p, const i
   if (bad) atomicOr(&sum->err, ERR_INPUT);
 }
 
-// An input with entries must come with a row array.
-__global__ void k_check_ptrs(PlanParams p, const int* const* __restrict__ cp, const int* const* __restrict__ ri,
-                             PlanSummary* __restrict__ sum) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= p.k) return;
-  if (cp[i][p.n] > 0 && ri[i] == nullptr) atomicOr(&sum->err, ERR_INPUT);
+// Copies a chunk of device pointers, passed by value, into a device table; the
+// first chunk of a plan also clears the plan summary and the dummy buffer.
+__global__ __launch_bounds__(256) void k_put_ptrs(PtrChunk c, const void** __restrict__ dst,
+                                                  PlanSummary* __restrict__ sum, unsigned* __restrict__ dummy) {
+  const int t = threadIdx.x;
+  if (t < c.count) dst[t] = c.p[t];
+  if (sum)
+    for (int i = t; i < (int)(sizeof(PlanSummary) / 4); i += 256) reinterpret_cast<int*>(sum)[i] = 0;
+  if (dummy)
+    for (int i = t; i < 1024; i += 256) dummy[i] = 0u;
 }
 
 // Exclusive scan, over blocks, of the per-block bin histograms (one bin at a time);
-// bin offsets; bin counts into the summary.  One block of 1024 threads.
+// bin offsets; bin counts into the summary.  One block; wavefront b scans bin b.
 __global__ __launch_bounds__(1024) void k_bin_scan(int nblk, int* __restrict__ hist, int* __restrict__ binoff,
                                                    PlanSummary* __restrict__ sum) {
-  __shared__ int scratch[1024 / 64 + 1];
+  static_assert(NBINS <= 1024 / 64, "one wavefront per bin");
   __shared__ int totals[NBINS];
-  for (int b = 0; b < NBINS; ++b) {
+  const int lane = lane_id(), b = threadIdx.x >> 6;
+  if (b < NBINS) {
     int carry = 0;
-    for (int base = 0; base < nblk; base += 1024) {
-      const int t = base + threadIdx.x;
+    for (int base = 0; base < nblk; base += 64) {
+      const int t = base + lane;
       const int v = t < nblk ? hist[t * NBINS + b] : 0;
-      int chunk = 0;
-      const int ex = block_excl_scan<1024>(v, scratch, &chunk);
-      if (t < nblk) hist[t * NBINS + b] = carry + ex;
-      carry += chunk;
+      const int incl = wave_scan_add(v);
+      if (t < nblk) hist[t * NBINS + b] = carry + incl - v;
+      carry += readlane(incl, 63);
     }
-    if (threadIdx.x == 0) totals[b] = carry;
+    if (lane == 0) totals[b] = carry;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     int acc = 0;
-    for (int b = 0; b < NBINS; ++b) {
-      binoff[b] = acc;
-      sum->bin_count[b] = totals[b];
-      acc += totals[b];
+    for (int bb = 0; bb < NBINS; ++bb) {
+      binoff[bb] = acc;
+      sum->bin_count[bb] = totals[bb];
+      acc += totals[bb];
     }
     binoff[NBINS] = acc;
   }
@@ -334,7 +341,8 @@ __global__ __launch_bounds__(256) void k_win_colsum(int n_wcols, const int* __re
   if (threadIdx.x == 0) colcnt[wcols[c]] = carry;
 }
 
-// ---- exclusive scan of int32 counts (three kernels) ----
+// ---- exclusive scan of int32 counts: tile sums, then each tile adds the sums of
+// the tiles before it (two kernels, no single-block pass) ----
 constexpr int SCAN_THREADS = 256, SCAN_PER_THREAD = 16, SCAN_TILE = SCAN_THREADS * SCAN_PER_THREAD;
 
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const int* __restrict__ in, long long len,
@@ -350,8 +358,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const int* __restr
   if (threadIdx.x == 0) bsum[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_top(long long* __restrict__ bsum, int nb,
-                                                   long long* __restrict__ total) {
+// Long inputs: exclusive scan of the tile sums in place, total into bsum[nb].
+__global__ __launch_bounds__(1024) void k_scan_top(long long* __restrict__ bsum, int nb) {
   __shared__ long long scratch[1024 / 64 + 1];
   long long carry = 0;
   for (int base = 0; base < nb; base += 1024) {
@@ -362,14 +370,37 @@ __global__ __launch_bounds__(1024) void k_scan_top(long long* __restrict__ bsum,
     if (t < nb) bsum[t] = carry + ex;
     carry += chunk;
   }
-  if (threadIdx.x == 0) *total = carry;
+  if (threadIdx.x == 0) bsum[nb] = carry;
 }
 
+// Block b: prefix = sum of bsum[0..b) and total = sum of bsum[0..nb), summed here
+// (short inputs) or read from k_scan_top's output (prefixed).  Block 0 also writes
+// out[len] and the total.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const int* __restrict__ in, long long len,
-                                                             const long long* __restrict__ bsum,
-                                                             const long long* __restrict__ total,
+                                                             const long long* __restrict__ bsum, int nb,
+                                                             bool prefixed, long long* __restrict__ total,
                                                              int* __restrict__ out, int* __restrict__ err) {
   __shared__ long long scratch[SCAN_THREADS / 64 + 1];
+  long long pre = 0, all = 0;
+  if (prefixed) {
+    pre = bsum[blockIdx.x];
+    all = bsum[nb];
+  } else {
+    for (int t = threadIdx.x; t < nb; t += SCAN_THREADS) {
+      const long long v = bsum[t];
+      pre += t < (int)blockIdx.x ? v : 0;
+      all += v;
+    }
+    pre = block_sum<SCAN_THREADS>(pre, scratch);
+    all = block_sum<SCAN_THREADS>(all, scratch);
+  }
+  if (all > INT_MAX) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      *total = all;
+      atomicOr(err, ERR_OVERFLOW);
+    }
+    return;
+  }
   const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_PER_THREAD;
   int v[SCAN_PER_THREAD];
   long long s = 0;
@@ -379,19 +410,17 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const int* __restri
     v[t] = x < len ? in[x] : 0;
     s += v[t];
   }
-  long long run = bsum[blockIdx.x] + block_excl_scan<SCAN_THREADS>(s, scratch);
-  const long long tot = *total;
-  if (tot > INT_MAX) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, ERR_OVERFLOW);
-    return;
-  }
+  long long run = pre + block_excl_scan<SCAN_THREADS>(s, scratch);
 #pragma unroll
   for (int t = 0; t < SCAN_PER_THREAD; ++t) {
     const long long x = base + t;
     if (x < len) out[x] = (int)run;
     run += v[t];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) out[len] = (int)tot;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    out[len] = (int)all;
+    *total = all;
+  }
 }
 
 // ---- host launchers ----
@@ -399,10 +428,22 @@ static inline unsigned grid_for(long long work, int per_block) {
   return (unsigned)((work + per_block - 1) / per_block);
 }
 
-void launch_bounds(const PlanParams& p, const int* const* d_cp, int* d_u, unsigned char* d_bin, int* d_colcnt,
-                   int* d_hist, PlanSummary* d_sum, hipStream_t s) {
-  if (p.n == 0) return;
-  k_bounds<<<grid_for(p.n, PLAN_THREADS), PLAN_THREADS, 0, s>>>(p, d_cp, d_u, d_bin, d_colcnt, d_hist, d_sum);
+void launch_bounds(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int* d_u,
+                   unsigned char* d_bin, int* d_colcnt, int* d_hist, PlanSummary* d_sum, hipStream_t s) {
+  const unsigned grid = p.n == 0 ? 1u : grid_for(p.n, PLAN_THREADS);
+  k_bounds<<<grid, PLAN_THREADS, 0, s>>>(p, d_cp, d_ri, d_u, d_bin, d_colcnt, d_hist, d_sum);
+}
+
+void launch_put_ptrs(const void* const* host_ptrs, int count, const void** d_dst, PlanSummary* d_sum,
+                     void* d_dummy, hipStream_t s) {
+  for (int base = 0; base < count || base == 0; base += PtrChunk::kMax) {
+    PtrChunk c;
+    c.count = count - base < PtrChunk::kMax ? count - base : PtrChunk::kMax;
+    for (int i = 0; i < c.count; ++i) c.p[i] = host_ptrs[base + i];
+    k_put_ptrs<<<1, 256, 0, s>>>(c, d_dst + base, base == 0 ? d_sum : nullptr,
+                                 base == 0 ? (unsigned*)d_dummy : nullptr);
+    if (count <= 0) break;
+  }
 }
 
 void launch_validate(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, PlanSummary* d_sum,
@@ -424,11 +465,6 @@ void launch_bin_scatter(const PlanParams& p, const unsigned char* d_bin, const i
 void launch_win_scan(const PlanParams& p, const int* d_list, const int* d_binoff, const int* d_u, int* d_wfirst,
                      PlanSummary* d_sum, hipStream_t s) {
   k_win_scan<<<1, 1024, 0, s>>>(p, d_list, d_binoff, d_u, d_wfirst, d_sum);
-}
-
-void launch_check_ptrs(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, PlanSummary* d_sum,
-                       hipStream_t s) {
-  k_check_ptrs<<<(p.k + 255) / 256, 256, 0, s>>>(p, d_cp, d_ri, d_sum);
 }
 
 void launch_win_fill(const PlanParams& p, int n_wcols, const int* d_wfirst, int* d_win_c, int* d_brow, int* d_bcol,
@@ -486,15 +522,10 @@ void launch_scan(const int* d_in, int64_t len, int* d_out, long long* d_total, i
                  hipStream_t s) {
   const int nb = (int)((len + SCAN_TILE - 1) / SCAN_TILE);
   long long* bsum = (long long*)d_tmp;
-  if (nb == 0) {
-    // empty input: out[0] = 0, total = 0
-    k_scan_top<<<1, 1024, 0, s>>>(bsum, 0, d_total);
-    k_scan_apply<<<1, SCAN_THREADS, 0, s>>>(d_in, 0, bsum, d_total, d_out, d_err);
-    return;
-  }
-  k_scan_reduce<<<nb, SCAN_THREADS, 0, s>>>(d_in, len, bsum);
-  k_scan_top<<<1, 1024, 0, s>>>(bsum, nb, d_total);
-  k_scan_apply<<<nb, SCAN_THREADS, 0, s>>>(d_in, len, bsum, d_total, d_out, d_err);
+  if (nb > 0) k_scan_reduce<<<nb, SCAN_THREADS, 0, s>>>(d_in, len, bsum);
+  const bool prefixed = nb > 1024;
+  if (prefixed) k_scan_top<<<1, 1024, 0, s>>>(bsum, nb);
+  k_scan_apply<<<nb > 0 ? nb : 1, SCAN_THREADS, 0, s>>>(d_in, len, bsum, nb, prefixed, d_total, d_out, d_err);
 }
 
 }  // namespace spk

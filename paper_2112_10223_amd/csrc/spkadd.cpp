@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <climits>
 #include <cstdarg>
 #include <cstdio>
@@ -126,6 +127,84 @@ class WorkspaceCache {
   std::map<std::pair<int, size_t>, std::vector<CachedBlock>> free_;
 };
 
+// Pinned host slots for the device -> host copies of the plan summary.  A copy into
+// pinned memory is asynchronous (a copy into pageable memory makes the host wait
+// on its own), and the host can watch the slot while the copy is queued.  Slots
+// come from 64 KiB hipHostMalloc chunks and are kept for the life of the process.
+class PinnedPool {
+ public:
+  static constexpr size_t kSlot = 256;
+  static_assert(sizeof(PlanSummary) <= kSlot, "slot size");
+  static PinnedPool& get() {
+    static PinnedPool* p = new PinnedPool();
+    return *p;
+  }
+  void* take() {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (free_.empty()) {
+      void* chunk = nullptr;
+      if (hipHostMalloc(&chunk, 64 * 1024, hipHostMallocPortable) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+      for (size_t o = 0; o < 64 * 1024; o += kSlot) free_.push_back((char*)chunk + o);
+    }
+    void* s = free_.back();
+    free_.pop_back();
+    return s;
+  }
+  void give(void* s) {
+    if (!s) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    free_.push_back(s);
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<void*> free_;
+};
+
+// Events, recycled: timing events for SPKADD_FLAG_TRACE (two hipEventRecord calls
+// per traced launch) and plain events for host waits.
+class EventPool {
+ public:
+  static EventPool& get() {
+    static EventPool* p = new EventPool(0u);
+    return *p;
+  }
+  static EventPool& plain() {
+    static EventPool* p = new EventPool(hipEventDisableTiming);
+    return *p;
+  }
+  explicit EventPool(unsigned flags) : flags_(flags) {}
+  hipEvent_t take() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      if (!free_.empty()) {
+        hipEvent_t e = free_.back();
+        free_.pop_back();
+        return e;
+      }
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, flags_) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return e;
+  }
+  void give(hipEvent_t e) {
+    if (!e) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    free_.push_back(e);
+  }
+
+ private:
+  unsigned flags_;
+  std::mutex mu_;
+  std::vector<hipEvent_t> free_;
+};
+
 struct TraceRec {
   const char* name;
   hipEvent_t a, b;
@@ -161,7 +240,8 @@ struct spkadd_plan_s {
   int* d_binoff = nullptr;
   int* d_list = nullptr;
   PlanSummary* d_sum = nullptr;
-  PlanSummary h_sum{};
+  PlanSummary* h_sum = nullptr;  // pinned slot
+  hipEvent_t ev_sum = nullptr;   // recorded after each summary copy
   int bin_count[NBINS] = {0};
   int binoff[NBINS + 1] = {0};
   // windows
@@ -178,7 +258,6 @@ struct spkadd_plan_s {
   void* d_dummy = nullptr;
   // scan
   void* d_scan_tmp = nullptr;
-  long long* d_total = nullptr;
   // table sizes per bin
   int ts_sym[NBINS] = {0}, ts_num[NBINS] = {0};
   // symbolic results
@@ -214,32 +293,41 @@ struct spkadd_plan_s {
 
 namespace {
 
-bool tracing(const spkadd_plan_s* p) { return (p->opts.flags & SPKADD_FLAG_TRACE) != 0; }
+bool tracing(const spkadd_plan_s* p, bool numeric) {
+  return (p->opts.flags & SPKADD_FLAG_TRACE) != 0 || (numeric && (p->opts.flags & SPKADD_FLAG_TRACE_NUMERIC) != 0);
+}
 
 struct TraceScope {
   spkadd_plan_s* p;
   const char* name;
   hipStream_t s;
   hipEvent_t a = nullptr;
-  TraceScope(spkadd_plan_s* p_, const char* n, hipStream_t s_) : p(p_), name(n), s(s_) {
-    if (tracing(p) && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+  TraceScope(spkadd_plan_s* p_, const char* n, hipStream_t s_, bool numeric = false) : p(p_), name(n), s(s_) {
+    if (!tracing(p, numeric)) return;
+    a = EventPool::get().take();
+    if (a && hipEventRecord(a, s) != hipSuccess) {
+      (void)hipGetLastError();
+      EventPool::get().give(a);
+      a = nullptr;
+    }
   }
   ~TraceScope() {
     if (!a) return;
-    hipEvent_t b = nullptr;
-    if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, s) == hipSuccess) {
+    hipEvent_t b = EventPool::get().take();
+    if (b && hipEventRecord(b, s) == hipSuccess) {
       p->trace.push_back({name, a, b});
     } else {
-      (void)hipEventDestroy(a);
-      if (b) (void)hipEventDestroy(b);
+      (void)hipGetLastError();
+      EventPool::get().give(a);
+      EventPool::get().give(b);
     }
   }
 };
 
 void clear_trace(spkadd_plan_s* p) {
   for (auto& t : p->trace) {
-    (void)hipEventDestroy(t.a);
-    (void)hipEventDestroy(t.b);
+    EventPool::get().give(t.a);
+    EventPool::get().give(t.b);
   }
   p->trace.clear();
 }
@@ -302,14 +390,48 @@ KArgs base_args(const spkadd_plan_s* p) {
   return a;
 }
 
-spkadd_status sync_summary(spkadd_plan_s* p, hipStream_t s) {
-  HIP_TRY(hipMemcpyAsync(&p->h_sum, p->d_sum, sizeof(PlanSummary), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+// The err field never holds this value on the device (it is a small bit mask).  The
+// host stores it before queuing a summary copy; the copy overwrites it.
+constexpr int kErrSentinel = 0x7fffffff;
+
+// Queues the copy of the device summary into the pinned slot.
+spkadd_status copy_summary(spkadd_plan_s* p, hipStream_t s) {
+  __atomic_store_n(&p->h_sum->err, kErrSentinel, __ATOMIC_RELAXED);
+  HIP_TRY(hipMemcpyAsync(p->h_sum, p->d_sum, sizeof(PlanSummary), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(p->ev_sum, s));
   return SPKADD_OK;
 }
 
+// Waits for the queued summary copy.  The host first watches the slot with no
+// runtime calls until the copy has overwritten the sentinel (polling the runtime
+// while kernels run slows their dispatch, and a blocking wait sleeps and wakes up
+// tens of microseconds late), then polls the copy's event, which completes a few
+// microseconds later.  Each stage falls back to a blocking wait after 20 ms.
+spkadd_status wait_summary(spkadd_plan_s* p) {
+  using clk = std::chrono::steady_clock;
+  const auto limit = std::chrono::milliseconds(20);
+  auto t0 = clk::now();
+  while (__atomic_load_n(&p->h_sum->err, __ATOMIC_RELAXED) == kErrSentinel)
+    if (clk::now() - t0 > limit) break;
+  t0 = clk::now();
+  for (;;) {
+    const hipError_t e = hipEventQuery(p->ev_sum);
+    if (e == hipSuccess) return SPKADD_OK;
+    if (e != hipErrorNotReady) return set_error(SPKADD_ERR_HIP, "summary copy: %s", hipGetErrorString(e));
+    if (clk::now() - t0 > limit) break;
+  }
+  (void)hipGetLastError();  // the not-ready status of the polls
+  HIP_TRY(hipEventSynchronize(p->ev_sum));
+  return SPKADD_OK;
+}
+
+spkadd_status sync_summary(spkadd_plan_s* p, hipStream_t s) {
+  spkadd_status st = copy_summary(p, s);
+  return st ? st : wait_summary(p);
+}
+
 spkadd_status check_device_err(spkadd_plan_s* p) {
-  const int e = p->h_sum.err;
+  const int e = p->h_sum->err;
   if (e & ERR_INPUT) return set_error(SPKADD_ERR_INVALID, "input validation failed (colptr, row range or order)");
   if (e & ERR_OVERFLOW) return set_error(SPKADD_ERR_OVERFLOW, "a count exceeds INT32_MAX");
   if (e & (ERR_PROBE | ERR_COUNT)) {
@@ -350,17 +472,16 @@ spkadd_status build_windows(spkadd_plan_s* p, hipStream_t s) {
   HIP_TRY(hipGetLastError());
   if ((st = sync_summary(p, s))) return st;
   p->levels = 0;
-  while (p->h_sum.pad > 0) {
+  while (p->h_sum->pad > 0) {
     if (++p->levels > 64) return set_error(SPKADD_ERR_HIP, "window refinement did not converge");
     // new window numbering: exclusive scan of the pieces per window
     int* d_newfirst = nullptr;
     void* tmp = nullptr;
     if ((st = p->alloc(&d_newfirst, (size_t)W + 1, s))) return st;
     if ((st = p->alloc((char**)&tmp, scan_tmp_bytes(W), s))) return st;
-    launch_scan(d_q, W, d_newfirst, p->d_total, &p->d_sum->err, tmp, s);
-    long long total = 0;
-    HIP_TRY(hipMemcpyAsync(&total, p->d_total, sizeof(total), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    launch_scan(d_q, W, d_newfirst, &p->d_sum->total, &p->d_sum->err, tmp, s);
+    if ((st = sync_summary(p, s))) return st;
+    const long long total = p->h_sum->total;
     if (total > INT_MAX / 2 || (total + nwc) * (long long)k > (long long)INT_MAX * 64)
       return set_error(SPKADD_ERR_OVERFLOW, "too many row windows (%lld)", total);
     const int W2 = (int)total;
@@ -467,6 +588,10 @@ void release_all(spkadd_plan_s* p) {
   hipStream_t s = p->last_stream;
   for (auto& a : p->allocs) WorkspaceCache::get().release(a.p, a.bytes, p->device, s);
   p->allocs.clear();
+  PinnedPool::get().give(p->h_sum);  // every copy into it was waited for
+  p->h_sum = nullptr;
+  EventPool::plain().give(p->ev_sum);
+  p->ev_sum = nullptr;
 }
 
 }  // namespace
@@ -560,23 +685,42 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
     return fail(set_error(SPKADD_ERR_INVALID, "window_cap / load_factor_num give too large numeric tables"));
 
   spkadd_status st;
-  const int nblk = (n + PLAN_THREADS - 1) / PLAN_THREADS;
-  void* ptrs = nullptr;
-  if ((st = p->alloc((char**)&ptrs, 3 * (size_t)k * sizeof(void*), stream))) return fail(st);
-  p->d_cp = (const int**)ptrs;
-  p->d_ri = p->d_cp + k;
-  p->d_va = (const void**)(p->d_ri + k);
-  if ((st = p->alloc(&p->d_u, n, stream))) return fail(st);
-  if ((st = p->alloc(&p->d_bin, n, stream))) return fail(st);
-  if ((st = p->alloc(&p->d_colcnt, n, stream))) return fail(st);
-  if ((st = p->alloc(&p->d_hist, (size_t)nblk * NBINS, stream))) return fail(st);
-  if ((st = p->alloc(&p->d_binoff, NBINS + 1, stream))) return fail(st);
-  if ((st = p->alloc(&p->d_list, n, stream))) return fail(st);
-  if ((st = p->alloc(&p->d_sum, 1, stream))) return fail(st);
-  if ((st = p->alloc(&p->d_wfirst, (size_t)n + 1, stream))) return fail(st);
-  if ((st = p->alloc(&p->d_total, 1, stream))) return fail(st);
-  if ((st = p->alloc((char**)&p->d_scan_tmp, scan_tmp_bytes(n), stream))) return fail(st);
-  if ((st = p->alloc((char**)&p->d_dummy, 4096, stream))) return fail(st);
+  const int nblk = n > 0 ? (n + PLAN_THREADS - 1) / PLAN_THREADS : 1;
+  p->h_sum = (PlanSummary*)PinnedPool::get().take();
+  if (!p->h_sum) return fail(set_error(SPKADD_ERR_OOM, "pinned host allocation failed"));
+  memset(p->h_sum, 0, sizeof(PlanSummary));
+  p->ev_sum = EventPool::plain().take();
+  if (!p->ev_sum) return fail(set_error(SPKADD_ERR_HIP, "event creation failed"));
+  // one workspace block for the fixed per-plan buffers
+  {
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+      const size_t o = off;
+      off += (bytes + 255) & ~(size_t)255;
+      return o;
+    };
+    const size_t o_ptrs = carve(3 * (size_t)k * sizeof(void*));
+    const size_t o_u = carve((size_t)n * 4), o_bin = carve((size_t)n), o_colcnt = carve((size_t)n * 4);
+    const size_t o_hist = carve((size_t)nblk * NBINS * 4), o_binoff = carve((NBINS + 1) * 4);
+    const size_t o_list = carve((size_t)n * 4), o_sum = carve(sizeof(PlanSummary));
+    const size_t o_wfirst = carve(((size_t)n + 1) * 4), o_scan = carve(scan_tmp_bytes(n));
+    const size_t o_dummy = carve(4096);
+    char* arena = nullptr;
+    if ((st = p->alloc(&arena, off, stream))) return fail(st);
+    p->d_cp = (const int**)(arena + o_ptrs);
+    p->d_ri = p->d_cp + k;
+    p->d_va = (const void**)(p->d_ri + k);
+    p->d_u = (int*)(arena + o_u);
+    p->d_bin = (unsigned char*)(arena + o_bin);
+    p->d_colcnt = (int*)(arena + o_colcnt);
+    p->d_hist = (int*)(arena + o_hist);
+    p->d_binoff = (int*)(arena + o_binoff);
+    p->d_list = (int*)(arena + o_list);
+    p->d_sum = (PlanSummary*)(arena + o_sum);
+    p->d_wfirst = (int*)(arena + o_wfirst);
+    p->d_scan_tmp = arena + o_scan;
+    p->d_dummy = arena + o_dummy;
+  }
   {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
@@ -593,13 +737,9 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
     return fail(set_error(SPKADD_ERR_HIP, "%s: %s", what, hipGetErrorString(e)));
   };
   hipError_t e;
-  if ((e = hipMemcpyAsync(p->d_cp, host_ptrs.data(), 2 * (size_t)k * sizeof(void*), hipMemcpyHostToDevice, stream)))
-    return hipfail(e, "pointer upload");
-  if ((e = hipMemsetAsync(p->d_sum, 0, sizeof(PlanSummary), stream))) return hipfail(e, "memset");
-  if ((e = hipMemsetAsync(p->d_dummy, 0, 4096, stream))) return hipfail(e, "memset");
   {
-    TraceScope t(p, "check_ptrs", stream);
-    launch_check_ptrs(p->pp, p->d_cp, p->d_ri, p->d_sum, stream);
+    TraceScope t(p, "put_ptrs", stream);
+    launch_put_ptrs(host_ptrs.data(), 2 * k, (const void**)p->d_cp, p->d_sum, p->d_dummy, stream);
   }
   if (o.flags & SPKADD_FLAG_VALIDATE) {
     TraceScope t(p, "validate", stream);
@@ -607,34 +747,42 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
   }
   {
     TraceScope t(p, "bounds", stream);
-    launch_bounds(p->pp, p->d_cp, p->d_u, p->d_bin, p->d_colcnt, p->d_hist, p->d_sum, stream);
+    launch_bounds(p->pp, p->d_cp, p->d_ri, p->d_u, p->d_bin, p->d_colcnt, p->d_hist, p->d_sum, stream);
   }
   {
     TraceScope t(p, "bin_scan", stream);
     launch_bin_scan(nblk, p->d_hist, p->d_binoff, p->d_sum, stream);
   }
+  if ((e = hipGetLastError())) return hipfail(e, "plan kernels");
+  // the host needs the bin counts; the column lists are built while it waits
+  if ((st = copy_summary(p, stream))) return fail(st);
   {
     TraceScope t(p, "bin_scatter", stream);
     launch_bin_scatter(p->pp, p->d_bin, p->d_hist, p->d_binoff, p->d_list, stream);
   }
-  {
-    TraceScope t(p, "win_scan", stream);
-    launch_win_scan(p->pp, p->d_list, p->d_binoff, p->d_u, p->d_wfirst, p->d_sum, stream);
-  }
   if ((e = hipGetLastError())) return hipfail(e, "plan kernels");
-  if ((st = sync_summary(p, stream))) return fail(st);
+  if ((st = wait_summary(p))) return fail(st);
   if ((st = check_device_err(p))) return fail(st);
   int acc = 0;
   for (int b = 0; b < NBINS; ++b) {
-    p->bin_count[b] = p->h_sum.bin_count[b];
+    p->bin_count[b] = p->h_sum->bin_count[b];
     p->binoff[b] = acc;
     acc += p->bin_count[b];
   }
   p->binoff[NBINS] = acc;
   p->n_wcols = p->bin_count[BIN_WIN];
-  p->n_windows = p->n_wcols ? p->h_sum.n_windows : 0;
+  p->n_windows = 0;
   if ((st = check_lds(p))) return fail(st);
-  if (p->n_windows > 0) {
+  if (p->n_wcols > 0) {
+    {
+      TraceScope t(p, "win_scan", stream);
+      launch_win_scan(p->pp, p->d_list, p->d_binoff, p->d_u, p->d_wfirst, p->d_sum, stream);
+    }
+    if ((e = hipGetLastError())) return hipfail(e, "plan kernels");
+    if ((st = sync_summary(p, stream))) return fail(st);
+    if ((st = check_device_err(p))) return fail(st);
+    p->n_windows = p->h_sum->n_windows;
+    if ((st = check_lds(p))) return fail(st);
     if ((st = build_windows(p, stream))) return fail(st);
     if ((st = check_device_err(p))) return fail(st);
   }
@@ -667,18 +815,17 @@ spkadd_status spkadd_symbolic(spkadd_plan_t p, int32_t* colptr_c, int64_t* nnz_c
   }
   {
     TraceScope t(p, "scan", stream);
-    launch_scan(p->d_colcnt, p->n, colptr_c, p->d_total, &p->d_sum->err, p->d_scan_tmp, stream);
+    launch_scan(p->d_colcnt, p->n, colptr_c, &p->d_sum->total, &p->d_sum->err, p->d_scan_tmp, stream);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     p->failed = true;
     return set_error(SPKADD_ERR_HIP, "symbolic kernels: %s", hipGetErrorString(e));
   }
-  long long total = 0;
-  HIP_TRY(hipMemcpyAsync(&total, p->d_total, sizeof(total), hipMemcpyDeviceToHost, stream));
   spkadd_status st = sync_summary(p, stream);
   if (st) return st;
   if ((st = check_device_err(p))) return st;
+  const long long total = p->h_sum->total;
   if (total > INT_MAX) return set_error(SPKADD_ERR_OVERFLOW, "nnz(B) = %lld exceeds INT32_MAX", total);
   p->colptr_c = colptr_c;
   p->nnz_c = total;
@@ -696,9 +843,12 @@ spkadd_status spkadd_numeric(spkadd_plan_t p, const void* const* values, int32_t
   if (!values) return set_error(SPKADD_ERR_INVALID, "values is NULL");
   if (p->nnz_c > 0 && (!rowidx_c || !values_c)) return set_error(SPKADD_ERR_INVALID, "output arrays are NULL");
   p->last_stream = stream;
-  std::vector<const void*> hv((size_t)p->k);
-  for (int i = 0; i < p->k; ++i) hv[i] = values[i];
-  HIP_TRY(hipMemcpyAsync((void*)p->d_va, hv.data(), (size_t)p->k * sizeof(void*), hipMemcpyHostToDevice, stream));
+  for (int i = 0; i < p->k; ++i)
+    if (!values[i] && p->h_sum->nnz_in > 0) return set_error(SPKADD_ERR_INVALID, "values[%d] is NULL", i);
+  {
+    TraceScope t(p, "put_ptrs_num", stream, true);
+    launch_put_ptrs((const void* const*)values, p->k, p->d_va, nullptr, nullptr, stream);
+  }
   KArgs a = base_args(p);
   a.alpha_q = p->alpha_num_q;
   a.colptr_c = p->colptr_c;
@@ -707,7 +857,7 @@ spkadd_status spkadd_numeric(spkadd_plan_t p, const void* const* values, int32_t
   for (int b = BIN_W1; b < NBINS; ++b) {
     const int cnt = b == BIN_WIN ? p->n_windows : p->bin_count[b];
     if (cnt == 0) continue;
-    TraceScope t(p, hash_kernel_name(b, true), stream);
+    TraceScope t(p, hash_kernel_name(b, true), stream, true);
     hipError_t e = launch_bin(p, b, true, a, stream);
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -729,7 +879,7 @@ spkadd_status spkadd_free(spkadd_plan_t p) {
 spkadd_status spkadd_get_stats(spkadd_plan_t p, spkadd_stats* out) {
   if (!p || !out) return set_error(SPKADD_ERR_INVALID, "NULL argument");
   spkadd_stats s{};
-  s.nnz_in = (int64_t)p->h_sum.nnz_in;
+  s.nnz_in = (int64_t)p->h_sum->nnz_in;
   s.nnz_out = p->sym_done ? p->nnz_c : -1;
   s.n_empty_cols = p->bin_count[BIN_EMPTY];
   for (int b = BIN_W1; b <= BIN_W16; ++b) s.n_wave_cols += p->bin_count[b];
@@ -739,16 +889,8 @@ spkadd_status spkadd_get_stats(spkadd_plan_t p, spkadd_stats* out) {
   s.window_levels = p->levels;
   s.window_cap = p->pp.cap_in;
   s.wave_max = p->pp.force_bin == 0 ? 1024 : p->pp.wave_max;
-  // device error flags raised by numeric passes since the last synchronisation
-  if (p->last_stream || true) {
-    int err = 0;
-    if (hipMemcpyAsync(&err, &p->d_sum->err, sizeof(int), hipMemcpyDeviceToHost, p->last_stream) == hipSuccess &&
-        hipStreamSynchronize(p->last_stream) == hipSuccess) {
-      p->h_sum.err = err;
-    } else {
-      (void)hipGetLastError();
-    }
-  }
+  // device error flags raised by numeric passes since the last wait
+  if (sync_summary(p, p->last_stream) != SPKADD_OK) (void)hipGetLastError();
   *out = s;
   return check_device_err(p);
 }

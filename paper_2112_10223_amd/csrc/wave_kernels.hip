@@ -286,9 +286,11 @@ __device__ __forceinline__ int bm_sym_unit(const KArgs& a, unsigned char* base, 
   unsigned* bm = reinterpret_cast<unsigned*>(bm4);
   for (int q = 0; q < a.bm_nq; ++q) bm4[q * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
   wave_sync();
+  // lanes past the end hold a copy of the unit's last row (or row 0 in a null unit)
+  // and OR nothing
 #pragma unroll
   for (int t = 0; t < E; ++t)
-    if (lane + 64 * t < u) atomicOr(&bm[rows[t] >> 5], 1u << (rows[t] & 31));
+    atomicOr(&bm[rows[t] >> 5], lane + 64 * t < u ? 1u << (rows[t] & 31) : 0u);
   wave_sync();
   int c = 0;
   for (int q = 0; q < a.bm_nq; ++q) {
@@ -304,8 +306,8 @@ __device__ __forceinline__ void bm_num_unit(const KArgs& a, unsigned char* base,
   const int lane = lane_id();
   uint4* bm4 = reinterpret_cast<uint4*>(base + a.off_bm);
   unsigned* bm = reinterpret_cast<unsigned*>(bm4);
-  unsigned short* pw = reinterpret_cast<unsigned short*>(base + a.off_pre);  // set bits below each word
-  V* bv = reinterpret_cast<V*>(base + a.off_bvals);
+  unsigned short* pw = reinterpret_cast<unsigned short*>(base + a.off_pre);  // set bits below each word pair
+  V* bv = reinterpret_cast<V*>(base + a.off_bvals);  // may overlay the bitmap (used after the ranks)
   int* br = reinterpret_cast<int*>(base + a.off_brows);
   const int nq = a.bm_nq;
   for (int q = 0; q < nq; ++q) bm4[q * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
@@ -313,26 +315,24 @@ __device__ __forceinline__ void bm_num_unit(const KArgs& a, unsigned char* base,
   bool first[E];
 #pragma unroll
   for (int t = 0; t < E; ++t) {
-    first[t] = false;
-    if (lane + 64 * t < u) {
-      const unsigned bit = 1u << (rows[t] & 31);
-      const unsigned old = atomicOr(&bm[rows[t] >> 5], bit);
-      first[t] = (old & bit) == 0;
-    }
+    // lanes past the end hold a copy of the unit's last row and OR nothing
+    const bool in = lane + 64 * t < u;
+    const unsigned bit = in ? 1u << (rows[t] & 31) : 0u;
+    const unsigned old = atomicOr(&bm[rows[t] >> 5], bit);
+    first[t] = in && (old & bit) == 0;
   }
   wave_sync();
-  // exclusive popcount prefix per word (ranks stay below 64 E <= 1024, so 16 bits
-  // hold them); lane handles the 4 words of group q*64 + lane
+  // exclusive popcount prefix per pair of words (ranks stay below 64 E <= 1024, so
+  // 16 bits hold them); lane handles the 4 words (2 pairs) of group q*64 + lane
   int carry = 0;
   for (int q = 0; q < nq; ++q) {
     const uint4 x = bm4[q * 64 + lane];
-    const int c0 = __popc(x.x), c1 = __popc(x.y), c2 = __popc(x.z), c3 = __popc(x.w);
-    const int n = c0 + c1 + c2 + c3;
+    const int c01 = __popc(x.x) + __popc(x.y), c23 = __popc(x.z) + __popc(x.w);
+    const int n = c01 + c23;
     const int incl = wave_scan_add(n);
-    const int p0 = carry + incl - n, p1 = p0 + c0, p2 = p1 + c1, p3 = p2 + c2;
+    const int p0 = carry + incl - n;
     carry += readlane(incl, 63);
-    reinterpret_cast<uint2*>(pw)[q * 64 + lane] =
-        make_uint2((unsigned)p0 | ((unsigned)p1 << 16), (unsigned)p2 | ((unsigned)p3 << 16));
+    reinterpret_cast<unsigned*>(pw)[q * 64 + lane] = (unsigned)p0 | ((unsigned)(p0 + c01) << 16);
   }
   int c = carry;
   if (c != cnt) {
@@ -347,14 +347,18 @@ __device__ __forceinline__ void bm_num_unit(const KArgs& a, unsigned char* base,
   for (int t = 0; t < E; ++t) {
     const int r = lane + 64 * t < u ? rows[t] : 0;
     const int w = r >> 5;
-    rk[t] = (int)pw[w] + __popc(bm[w] & ((1u << (r & 31)) - 1u));
+    const uint2 pr = reinterpret_cast<const uint2*>(bm)[w >> 1];
+    const unsigned word = (w & 1) ? pr.y : pr.x;
+    rk[t] = (int)pw[w >> 1] + ((w & 1) ? __popc(pr.x) : 0) + __popc(word & ((1u << (r & 31)) - 1u));
   }
+  wave_sync();  // the bitmap is read for the last time above
+  // entries that are not first write into per-lane sink slots 64 E + lane
 #pragma unroll
-  for (int t = 0; t < E; ++t)
-    if (first[t]) {
-      bv[rk[t]] = vals[t];
-      br[rk[t]] = rows[t];
-    }
+  for (int t = 0; t < E; ++t) {
+    const int d = first[t] ? rk[t] : 64 * E + lane;
+    bv[d] = vals[t];
+    br[d] = rows[t];
+  }
   wave_sync();
 #pragma unroll
   for (int t = 0; t < E; ++t)
@@ -384,7 +388,7 @@ struct UnitRegs {
 // (pointers) and t+1 (entries), then process unit t.
 // Units t >= nu are null units (no entries, no output): every step runs the same
 // instruction sequence, so the compiler keeps the next unit's loads in flight.
-template <int E, bool NUM, typename V>
+template <int E, bool NUM, typename V, bool BM>
 __device__ __forceinline__ void pipe_step(const KArgs& a, unsigned char* base, int t, int nu, int ucol,
                                           long long cpp, long long rip, long long vap, int& ms, int& me, int& mc,
                                           UnitRegs<E, NUM, V>& cur, UnitRegs<E, NUM, V>& nxt) {
@@ -403,11 +407,11 @@ __device__ __forceinline__ void pipe_step(const KArgs& a, unsigned char* base, i
     wave_sync();
     issue_unit_loads<E, NUM, V>(a, base, adj, adjv, nxt.u, nxt.rows, nxt.vals);
   }
-  if (NUM && a.bm_nq > 0) {
+  if constexpr (NUM && BM) {
     bm_num_unit<E, V>(a, base, cur.u, cur.cnt, cur.o0, cur.rows, cur.vals);
-  } else if (NUM) {
+  } else if constexpr (NUM) {
     num_unit<E, V>(a, base, cur.u, cur.cnt, cur.o0, cur.rows, cur.vals);
-  } else if (a.bm_nq > 0) {
+  } else if constexpr (BM) {
     const int cnt = bm_sym_unit<E>(a, base, cur.u, cur.rows);
     const long long dst = cur.j >= 0 ? (long long)(a.colcnt + cur.j) : (long long)a.dummy + 2048 + 8LL * lane;
     if (lane == 0) gstore<int>(dst, cnt);
@@ -426,7 +430,7 @@ __device__ __forceinline__ void pipe_step(const KArgs& a, unsigned char* base, i
   }
 }
 
-template <int E, bool NUM, typename V>
+template <int E, bool NUM, typename V, bool BM>
 __global__ __launch_bounds__(256) void k_wave_pipe(KArgs a, const int* __restrict__ list, int nunits) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = lane_id(), w = threadIdx.x >> 6;
@@ -460,8 +464,8 @@ __global__ __launch_bounds__(256) void k_wave_pipe(KArgs a, const int* __restric
   }
   const int steps = (nu + 1) & ~1;
   for (int t = 0; t < steps; t += 2) {
-    pipe_step<E, NUM, V>(a, base, t, nu, ucol, cpp, rip, vap, ms, me, mc, A, B);
-    pipe_step<E, NUM, V>(a, base, t + 1, nu, ucol, cpp, rip, vap, ms, me, mc, B, A);
+    pipe_step<E, NUM, V, BM>(a, base, t, nu, ucol, cpp, rip, vap, ms, me, mc, A, B);
+    pipe_step<E, NUM, V, BM>(a, base, t + 1, nu, ucol, cpp, rip, vap, ms, me, mc, B, A);
   }
 }
 
@@ -476,11 +480,14 @@ void lds_layout_pipe(int bin, bool numeric, int vbytes, int ts_max, int bm_nq, K
   int bm_bytes = 0;
   a.bm_nq = bm_nq;
   if (bm_nq > 0) {
+    // bitmap (nq x 1 KiB), pair prefix (nq x 256 B); numeric: the values and rows
+    // staged by rank overlay the bitmap when they fit in it, else follow
     a.off_bm = 0;
     a.off_pre = bm_nq * 256 * 4;
-    a.off_bvals = a.off_pre + bm_nq * 256 * 2;
-    a.off_brows = a.off_bvals + 64 * E * vbytes;
-    bm_bytes = numeric ? a.off_brows + 64 * E * 4 : a.off_pre;
+    const int staged = 64 * (E + 1) * (vbytes + 4);  // 64 E positions + 64 sink slots
+    a.off_bvals = staged <= a.off_pre ? 0 : a.off_pre + bm_nq * 256;
+    a.off_brows = a.off_bvals + 64 * (E + 1) * vbytes;
+    bm_bytes = !numeric ? a.off_pre : staged <= a.off_pre ? a.off_pre + bm_nq * 256 : a.off_brows + 64 * (E + 1) * 4;
   }
   int off = bm_nq > 0 ? bm_bytes : hash_bytes;
   off = (off + 15) & ~15;
@@ -497,22 +504,30 @@ void lds_layout_pipe(int bin, bool numeric, int vbytes, int ts_max, int bm_nq, K
   a.ts_max = ts_max;
 }
 
+template <int E, bool NUM, typename V>
+static void launch_pipe_e(const KArgs& a, const int* list, int n, unsigned blocks, size_t lds, hipStream_t s) {
+  if (a.bm_nq > 0)
+    k_wave_pipe<E, NUM, V, true><<<blocks, 256, lds, s>>>(a, list, n);
+  else
+    k_wave_pipe<E, NUM, V, false><<<blocks, 256, lds, s>>>(a, list, n);
+}
+
 template <bool NUM, typename V>
 static hipError_t launch_pipe_t(int bin, const KArgs& a, const int* list, int n, hipStream_t s) {
   const int waves = (n + a.upw - 1) / a.upw;
-  const int blocks = (waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  const unsigned blocks = (unsigned)((waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK);
   const size_t lds = (size_t)a.slice_bytes * WAVES_PER_BLOCK;
   switch (bin) {
-    case BIN_W1: k_wave_pipe<1, NUM, V><<<blocks, 256, lds, s>>>(a, list, n); break;
-    case BIN_W2: k_wave_pipe<2, NUM, V><<<blocks, 256, lds, s>>>(a, list, n); break;
-    case BIN_W3: k_wave_pipe<3, NUM, V><<<blocks, 256, lds, s>>>(a, list, n); break;
-    case BIN_W4: k_wave_pipe<4, NUM, V><<<blocks, 256, lds, s>>>(a, list, n); break;
-    case BIN_W5: k_wave_pipe<5, NUM, V><<<blocks, 256, lds, s>>>(a, list, n); break;
-    case BIN_W6: k_wave_pipe<6, NUM, V><<<blocks, 256, lds, s>>>(a, list, n); break;
-    case BIN_W8: k_wave_pipe<8, NUM, V><<<blocks, 256, lds, s>>>(a, list, n); break;
-    case BIN_W10: k_wave_pipe<10, NUM, V><<<blocks, 256, lds, s>>>(a, list, n); break;
-    case BIN_W12: k_wave_pipe<12, NUM, V><<<blocks, 256, lds, s>>>(a, list, n); break;
-    case BIN_W16: k_wave_pipe<16, NUM, V><<<blocks, 256, lds, s>>>(a, list, n); break;
+    case BIN_W1: launch_pipe_e<1, NUM, V>(a, list, n, blocks, lds, s); break;
+    case BIN_W2: launch_pipe_e<2, NUM, V>(a, list, n, blocks, lds, s); break;
+    case BIN_W3: launch_pipe_e<3, NUM, V>(a, list, n, blocks, lds, s); break;
+    case BIN_W4: launch_pipe_e<4, NUM, V>(a, list, n, blocks, lds, s); break;
+    case BIN_W5: launch_pipe_e<5, NUM, V>(a, list, n, blocks, lds, s); break;
+    case BIN_W6: launch_pipe_e<6, NUM, V>(a, list, n, blocks, lds, s); break;
+    case BIN_W8: launch_pipe_e<8, NUM, V>(a, list, n, blocks, lds, s); break;
+    case BIN_W10: launch_pipe_e<10, NUM, V>(a, list, n, blocks, lds, s); break;
+    case BIN_W12: launch_pipe_e<12, NUM, V>(a, list, n, blocks, lds, s); break;
+    case BIN_W16: launch_pipe_e<16, NUM, V>(a, list, n, blocks, lds, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

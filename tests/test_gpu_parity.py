@@ -267,6 +267,22 @@ def test_trace_records_kernels():
     assert "bounds" in names and any(x.startswith("sym_") for x in names) and any(x.startswith("num_") for x in names)
     assert all(ms >= 0 for _, ms in tr)
     plan.free()
+    # numeric-only tracing records nothing before spkadd_numeric, then its launches
+    plan = binding.spkadd_plan(b.m, b.n, cps, ris, binding.SPKADD_F32,
+                               _opts(flags=binding.SPKADD_FLAG_TRACE_NUMERIC))
+    binding.spkadd_symbolic(plan, cp)
+    assert binding.spkadd_trace(plan) == []
+    binding.spkadd_numeric(plan, vas, r, v)
+    names = [t[0] for t in binding.spkadd_trace(plan)]
+    assert any(x.startswith("num_") for x in names)
+    assert all(x.startswith(("num_", "put_ptrs_num")) for x in names)
+    # a NULL value pointer of a non-empty input is rejected on the host
+    import ctypes
+    nulls = (ctypes.c_void_p * b.k)(*([None] * b.k))
+    st = binding.lib().spkadd_numeric(plan.handle, ctypes.cast(nulls, ctypes.c_void_p), r.data_ptr(), v.data_ptr(),
+                                      binding._stream_ptr(None))
+    assert st == binding.SPKADD_ERR_INVALID
+    plan.free()
 
 
 # ---- full-size workloads: properties on every column, the oracle on sampled columns ----
