@@ -48,14 +48,27 @@ WORKLOADS = {
 WAVE_E = [1, 2, 3, 4, 5, 6, 8, 10, 12, 16]
 
 
-def kernel_of_column(u: np.ndarray, cap: int, wave_max: int = 1024) -> np.ndarray:
+def kernel_of_column(u: np.ndarray, cap: int, wave_max: int = 1024, merge: bool = True) -> np.ndarray:
     """Name of the numeric kernel each column goes to under the default options
-    (mirrors the library's binning by u_j)."""
+    (mirrors the library's binning by u_j, and its merging of two adjacent
+    populous wave bins)."""
     names = np.empty(u.shape[0], dtype=object)
     names[:] = "empty"
     e = (u + 63) // 64
     for E in reversed(WAVE_E):
         names[(u > 0) & (u <= wave_max) & (e <= E)] = f"num_wave_e{E}"
+    if merge:
+        counts = {E: int(np.sum(names == f"num_wave_e{E}")) for E in WAVE_E}
+        total = sum(counts.values())
+        prev = None
+        for E in WAVE_E:
+            if counts[E] == 0:
+                continue
+            if prev is not None and 16 * counts[prev] >= total and 16 * counts[E] >= total and 2 * E <= 3 * prev:
+                names[names == f"num_wave_e{prev}"] = f"num_wave_e{E}"
+                prev = None
+            else:
+                prev = E
     names[(u > wave_max) & (u <= min(cap, 2048))] = "num_wg256"
     names[(u > max(wave_max, min(cap, 2048))) & (u <= cap)] = "num_wg512"
     names[u > cap] = "num_window"

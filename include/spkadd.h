@@ -92,7 +92,10 @@ typedef struct spkadd_opts {
                             1 = hash tables only, 2 = bitmap wherever it fits (m <= 131072) */
   float bitmap_ratio;    /* auto mode: use the bitmap when ceil(m / 8192) <= bitmap_ratio * E,
                             E = ceil(u_max / 64) of the bin; 0 = default (1.0) */
-  int32_t reserved[2];
+  int32_t wave_merge;    /* 0 = merge two adjacent wave bins that each hold >= 1/16 of the
+                            wave columns (one kernel then reads neighbouring columns together);
+                            1 = keep every wave bin separate */
+  int32_t reserved[1];
 } spkadd_opts;
 
 typedef struct spkadd_plan_s* spkadd_plan_t;

@@ -32,7 +32,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("force_bin", ctypes.c_int32), ("window_cap", ctypes.c_int32),
                 ("hash_mode", ctypes.c_int32), ("wave_max", ctypes.c_int32), ("load_factor_sym", ctypes.c_float),
                 ("load_factor_num", ctypes.c_float), ("window_fill", ctypes.c_float),
-                ("accum_mode", ctypes.c_int32), ("bitmap_ratio", ctypes.c_float), ("reserved", ctypes.c_int32 * 2)]
+                ("accum_mode", ctypes.c_int32), ("bitmap_ratio", ctypes.c_float), ("wave_merge", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 class Stats(ctypes.Structure):

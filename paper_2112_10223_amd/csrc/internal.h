@@ -104,7 +104,8 @@ void launch_bounds(const PlanParams& p, const int* const* d_cp, const int* const
                    unsigned char* d_bin, int* d_colcnt, int* d_hist, PlanSummary* d_sum, hipStream_t s);
 void launch_validate(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, PlanSummary* d_sum,
                      hipStream_t s);
-void launch_bin_scan(int nblk, int* d_hist, int* d_binoff, PlanSummary* d_sum, hipStream_t s);
+// d_binoff holds 2 NBINS + 1 ints: offsets (NBINS + 1), then the merge map.
+void launch_bin_scan(int nblk, bool merge, int* d_hist, int* d_binoff, PlanSummary* d_sum, hipStream_t s);
 void launch_bin_scatter(const PlanParams& p, const unsigned char* d_bin, const int* d_hist, const int* d_binoff,
                         int* d_list, hipStream_t s);
 void launch_win_scan(const PlanParams& p, const int* d_list, const int* d_binoff, const int* d_u, int* d_wfirst,

@@ -104,31 +104,76 @@ __global__ __launch_bounds__(256) void k_put_ptrs(PtrChunk c, const void** __res
     for (int i = t; i < 1024; i += 256) dummy[i] = 0u;
 }
 
-// Exclusive scan, over blocks, of the per-block bin histograms (one bin at a time);
-// bin offsets; bin counts into the summary.  One block; wavefront b scans bin b.
-__global__ __launch_bounds__(1024) void k_bin_scan(int nblk, int* __restrict__ hist, int* __restrict__ binoff,
-                                                   PlanSummary* __restrict__ sum) {
+// Exclusive scan, over blocks, of the per-block bin histograms; bin offsets; bin
+// counts into the summary.  One block of 1024 threads.
+//
+// Wave-bin merging: each input column's rows are only a few dozen bytes, less than
+// a cache line, and neighbouring columns share lines.  When a column population is
+// split between two adjacent wave bins (as a Poisson column length around a bin
+// edge is), the two kernels fetch the shared lines twice.  With merge set, two
+// adjacent non-empty wave bins that each hold at least 1/16 of the wave columns,
+// and whose E differ by at most 3/2, become one bin (the larger E); a column of
+// the smaller bin then runs with some lanes idle.  binoff[NBINS + 1 + b] receives
+// the bin that bin b's columns go to.
+__global__ __launch_bounds__(1024) void k_bin_scan(int nblk, int merge, int* __restrict__ hist,
+                                                   int* __restrict__ binoff, PlanSummary* __restrict__ sum) {
   static_assert(NBINS <= 1024 / 64, "one wavefront per bin");
   __shared__ int totals[NBINS];
+  __shared__ int map[NBINS];
+  __shared__ int mtot[NBINS];
   const int lane = lane_id(), b = threadIdx.x >> 6;
   if (b < NBINS) {
+    int s = 0;
+    for (int base = 0; base < nblk; base += 64) {
+      const int t = base + lane;
+      s += t < nblk ? hist[t * NBINS + b] : 0;
+    }
+    s = wave_total_add(s);
+    if (lane == 0) totals[b] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int x = 0; x < NBINS; ++x) map[x] = x;
+    if (merge) {
+      long long wave_cols = 0;
+      for (int x = BIN_W1; x <= BIN_W16; ++x) wave_cols += totals[x];
+      int prev = -1;
+      for (int x = BIN_W1; x <= BIN_W16; ++x) {
+        if (totals[x] == 0) continue;
+        if (prev >= 0 && 16LL * totals[prev] >= wave_cols && 16LL * totals[x] >= wave_cols &&
+            2 * wave_bin_E(x) <= 3 * wave_bin_E(prev)) {
+          map[prev] = x;  // pairs only: x takes no further merge
+          prev = -1;
+        } else {
+          prev = x;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // wavefront b scans, over blocks, the per-block counts of the bins mapped to b
+  if (b < NBINS && map[b] == b) {
     int carry = 0;
     for (int base = 0; base < nblk; base += 64) {
       const int t = base + lane;
-      const int v = t < nblk ? hist[t * NBINS + b] : 0;
+      int v = 0;
+      if (t < nblk)
+        for (int x = 0; x < NBINS; ++x) v += map[x] == b ? hist[t * NBINS + x] : 0;
       const int incl = wave_scan_add(v);
       if (t < nblk) hist[t * NBINS + b] = carry + incl - v;
       carry += readlane(incl, 63);
     }
-    if (lane == 0) totals[b] = carry;
+    if (lane == 0) mtot[b] = carry;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     int acc = 0;
     for (int bb = 0; bb < NBINS; ++bb) {
+      const int c = map[bb] == bb ? mtot[bb] : 0;
       binoff[bb] = acc;
-      sum->bin_count[bb] = totals[bb];
-      acc += totals[bb];
+      binoff[NBINS + 1 + bb] = map[bb];
+      sum->bin_count[bb] = c;
+      acc += c;
     }
     binoff[NBINS] = acc;
   }
@@ -142,7 +187,7 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_bin_scatter(PlanParams p, cons
   __shared__ int wc[PLAN_THREADS / 64][NBINS];
   const int j = blockIdx.x * PLAN_THREADS + threadIdx.x;
   const int lane = lane_id(), w = threadIdx.x >> 6;
-  const int b = j < p.n ? (int)bin[j] : -1;
+  const int b = j < p.n ? binoff[NBINS + 1 + (int)bin[j]] : -1;  // bin after merging
   int rank = 0;
   for (int bb = 0; bb < NBINS; ++bb) {
     const uint64_t mk = ballot(b == bb);
@@ -452,8 +497,8 @@ void launch_validate(const PlanParams& p, const int* const* d_cp, const int* con
   k_validate<<<grid_for(p.n, PLAN_THREADS), PLAN_THREADS, 0, s>>>(p, d_cp, d_ri, d_sum);
 }
 
-void launch_bin_scan(int nblk, int* d_hist, int* d_binoff, PlanSummary* d_sum, hipStream_t s) {
-  k_bin_scan<<<1, 1024, 0, s>>>(nblk, d_hist, d_binoff, d_sum);
+void launch_bin_scan(int nblk, bool merge, int* d_hist, int* d_binoff, PlanSummary* d_sum, hipStream_t s) {
+  k_bin_scan<<<1, 1024, 0, s>>>(nblk, merge ? 1 : 0, d_hist, d_binoff, d_sum);
 }
 
 void launch_bin_scatter(const PlanParams& p, const unsigned char* d_bin, const int* d_hist, const int* d_binoff,

@@ -636,6 +636,7 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
   if (o.accum_mode < 0 || o.accum_mode > 2) return set_error(SPKADD_ERR_INVALID, "bad accum_mode %d", o.accum_mode);
   if (!(o.bitmap_ratio >= 0.f && o.bitmap_ratio <= 64.f))
     return set_error(SPKADD_ERR_INVALID, "bitmap_ratio must be in [0, 64]");
+  if (o.wave_merge < 0 || o.wave_merge > 1) return set_error(SPKADD_ERR_INVALID, "bad wave_merge %d", o.wave_merge);
 
   auto* p = new (std::nothrow) spkadd_plan_s();
   if (!p) return set_error(SPKADD_ERR_OOM, "host allocation failed");
@@ -701,7 +702,7 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
     };
     const size_t o_ptrs = carve(3 * (size_t)k * sizeof(void*));
     const size_t o_u = carve((size_t)n * 4), o_bin = carve((size_t)n), o_colcnt = carve((size_t)n * 4);
-    const size_t o_hist = carve((size_t)nblk * NBINS * 4), o_binoff = carve((NBINS + 1) * 4);
+    const size_t o_hist = carve((size_t)nblk * NBINS * 4), o_binoff = carve((2 * NBINS + 1) * 4);
     const size_t o_list = carve((size_t)n * 4), o_sum = carve(sizeof(PlanSummary));
     const size_t o_wfirst = carve(((size_t)n + 1) * 4), o_scan = carve(scan_tmp_bytes(n));
     const size_t o_dummy = carve(4096);
@@ -751,7 +752,7 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
   }
   {
     TraceScope t(p, "bin_scan", stream);
-    launch_bin_scan(nblk, p->d_hist, p->d_binoff, p->d_sum, stream);
+    launch_bin_scan(nblk, o.wave_merge == 0, p->d_hist, p->d_binoff, p->d_sum, stream);
   }
   if ((e = hipGetLastError())) return hipfail(e, "plan kernels");
   // the host needs the bin counts; the column lists are built while it waits

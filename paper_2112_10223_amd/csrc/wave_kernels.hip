@@ -1,19 +1,22 @@
-// Wave-bin kernels with a per-wavefront pipeline over consecutive columns.
+// Wave-bin kernels: one wavefront per column, with a per-wavefront pipeline over
+// its columns.
 //
-// One wavefront owns `upw` consecutive units (columns) of a bin.  While it
-// accumulates column t in its LDS table, the column pointers of column t+2 and the
-// row (and value) loads of column t+1 are already in flight.  The two register
-// sets alternate, and the loop is unrolled by two so that no register copy forces
-// a wait.  Lane i < k keeps the base pointers of input i for the whole run
-// (k <= 64).
+// Wavefront gw of a launch of G wavefronts takes the bin's units gw, gw + G,
+// gw + 2G, ... (at most 64).  While it accumulates one column in LDS, the column
+// pointers of the column after next and the row (and value) loads of the next
+// column are already in flight.  Two register sets alternate, and the loop is
+// unrolled by two so that no register copy forces a wait.  Lane i < k keeps the
+// base pointers of input i for the whole run (k <= 64).
 //
-// Symbolic (Algorithm 6): compare-and-swap claims in a key-only LDS table.  All
-// E entries of a lane are claimed together, then the colliding ones probe on.
-// Numeric (Algorithm 5): the same claims on (key, value) tables plus LDS atomic
-// adds.  The table is then read into registers and bucketed by the top 8 bits of
-// (row - min row).  Each entry is ranked inside its bucket by counting the smaller
-// keys; rows are unique, so the bucket order needs no stability.  The sorted column
-// is written out coalesced.
+// Two accumulators, chosen per launch:
+//  * hash (Algorithms 5 and 6): linear-probing LDS tables with compare-and-swap
+//    claims; the numeric table is then compacted, bucketed by the top 8 bits of
+//    (row - min row) and ranked inside each bucket, which sorts the column;
+//  * bitmap: one bit per row of the matrix in LDS (the dense accumulator of
+//    Algorithm 4 with the value array indexed by rank); the rank of a row among
+//    the set bits is its output position, so the column comes out sorted with no
+//    probing and no sort.
+// Either way the sorted column is written out coalesced.
 #include "hash_common.h"
 
 namespace spk {
@@ -377,6 +380,41 @@ __device__ __forceinline__ void bm_num_unit(const KArgs& a, unsigned char* base,
   }
 }
 
+// Marks the entry registers of a unit as needed here.  Called before the next
+// unit's loads are issued: the compiler then waits for these loads with the
+// previous unit's stores still in flight (stores count in vmcnt on this target,
+// and a wait placed after newer loads would also wait for them).
+template <int E, bool NUM, typename V>
+__device__ __forceinline__ void require_loaded(const int (&rows)[E], const V (&vals)[E]) {
+#pragma unroll
+  for (int t = 0; t < E; ++t) {
+    asm volatile("" ::"v"(rows[t]));
+    if constexpr (NUM) asm volatile("" ::"v"(vals[t]));
+  }
+}
+
+// Stores into the write sink as many store instructions as one pipeline step
+// issues, so that the pipeline loop is entered with the same memory-counter history
+// as its back edge (loads, then one unit's stores).  Otherwise the compiler merges
+// the two histories at the loop head into a wait for every outstanding store.
+template <int E, bool NUM, typename V>
+__device__ __forceinline__ void prime_stores(const KArgs& a) {
+  const int lane = lane_id();
+  const long long dmy = (long long)a.dummy + 2048 + 8LL * lane;
+  // (the empty asm statements keep the compiler from merging the repeated stores)
+  if constexpr (NUM) {
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+      gstore<int>(dmy, 0);
+      asm volatile("" ::: "memory");
+      gstore<V>(dmy, V(0));
+      asm volatile("" ::: "memory");
+    }
+  } else {
+    gstore<int>(dmy, 0);
+  }
+}
+
 template <int E, bool NUM, typename V>
 struct UnitRegs {
   int rows[E];
@@ -393,6 +431,7 @@ __device__ __forceinline__ void pipe_step(const KArgs& a, unsigned char* base, i
                                           long long cpp, long long rip, long long vap, int& ms, int& me, int& mc,
                                           UnitRegs<E, NUM, V>& cur, UnitRegs<E, NUM, V>& nxt) {
   const int lane = lane_id();
+  require_loaded<E, NUM, V>(cur.rows, cur.vals);
   {
     const int b = (t + 1) & 1;
     long long* adj = (long long*)(base + a.off_adj) + 64 * b;
@@ -413,8 +452,10 @@ __device__ __forceinline__ void pipe_step(const KArgs& a, unsigned char* base, i
     num_unit<E, V>(a, base, cur.u, cur.cnt, cur.o0, cur.rows, cur.vals);
   } else if constexpr (BM) {
     const int cnt = bm_sym_unit<E>(a, base, cur.u, cur.rows);
-    const long long dst = cur.j >= 0 ? (long long)(a.colcnt + cur.j) : (long long)a.dummy + 2048 + 8LL * lane;
-    if (lane == 0) gstore<int>(dst, cnt);
+    // one unconditional store instruction: lane 0 writes the count, the other
+    // lanes (and null units) write into their write-sink slots
+    const long long dmy = (long long)a.dummy + 2048 + 8LL * lane;
+    gstore<int>(lane == 0 && cur.j >= 0 ? (long long)(a.colcnt + cur.j) : dmy, cnt);
     wave_sync();
   } else {
     int* T = (int*)base;
@@ -424,8 +465,8 @@ __device__ __forceinline__ void pipe_step(const KArgs& a, unsigned char* base, i
     wave_sync();
     const int newc = insert_batch<E, false, V>(T, nullptr, TS, a.hash_mode, cur.u, cur.rows, cur.vals, a.err);
     const int cnt = wave_total_add(newc);
-    const long long dst = cur.j >= 0 ? (long long)(a.colcnt + cur.j) : (long long)a.dummy + 2048 + 8LL * lane;
-    if (lane == 0) gstore<int>(dst, cnt);
+    const long long dmy = (long long)a.dummy + 2048 + 8LL * lane;
+    gstore<int>(lane == 0 && cur.j >= 0 ? (long long)(a.colcnt + cur.j) : dmy, cnt);
     wave_sync();
   }
 }
@@ -434,16 +475,20 @@ template <int E, bool NUM, typename V, bool BM>
 __global__ __launch_bounds__(256) void k_wave_pipe(KArgs a, const int* __restrict__ list, int nunits) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = lane_id(), w = threadIdx.x >> 6;
+  // Units are dealt out with stride G (all wavefronts of the launch): at any time
+  // the wavefronts of one XCD (consecutive gw after the remap) work on neighbouring
+  // columns, whose input rows share cache lines, instead of each wavefront walking a
+  // column range of its own (too many partly used lines for the L2).
+  const int G = (int)gridDim.x * WAVES_PER_BLOCK;
   const int gw = xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + w;
-  const int ub = gw * a.upw;
-  const int nu = min(a.upw, nunits - ub);
-  if (nu <= 0) return;  // no block-wide barriers in this kernel
+  if (gw >= nunits) return;  // no block-wide barriers in this kernel
+  const int nu = (nunits - gw + G - 1) / G;  // <= upw <= 64
   unsigned char* base = smem + w * a.slice_bytes;
   const int li = lane < a.k ? lane : a.k - 1;
   const long long cpp = (long long)a.cp[li];
   const long long rip = (long long)a.ri[li];
   const long long vap = NUM ? (long long)a.va[li] : 0;
-  const int ucol = lane < nu ? list[ub + lane] : 0;
+  const int ucol = lane < nu ? list[gw + lane * G] : 0;
 
   UnitRegs<E, NUM, V> A, B;
   int ms = 0, me = 0, mc = 0;
@@ -462,6 +507,7 @@ __global__ __launch_bounds__(256) void k_wave_pipe(KArgs a, const int* __restric
     wave_sync();
     issue_unit_loads<E, NUM, V>(a, base, adj, adjv, A.u, A.rows, A.vals);
   }
+  prime_stores<E, NUM, V>(a);
   const int steps = (nu + 1) & ~1;
   for (int t = 0; t < steps; t += 2) {
     pipe_step<E, NUM, V, BM>(a, base, t, nu, ucol, cpp, rip, vap, ms, me, mc, A, B);

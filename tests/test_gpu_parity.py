@@ -115,6 +115,20 @@ def test_accum_modes(mode, shape):
     assert_matches(batch, run_gpu(batch, _opts(accum_mode=mode, bitmap_ratio=4.0)), oracle.spkadd(batch))
 
 
+@pytest.mark.parametrize("merge", [0, 1])
+def test_wave_bin_merging(merge):
+    """Merged and separate wave bins give the same result.  Column lengths
+    Poisson(40 * 8) straddle the E=5 / E=6 edge, so the auto rule merges them."""
+    note(f"wave_merge={merge}")
+    for values, exact in (("int32f", True), ("f32", False)):
+        batch = workloads.er(20000, 600, 8, 40.0, seed=77 + merge, values=values)
+        got = run_gpu(batch, _opts(wave_merge=merge))
+        assert_matches(batch, got, oracle.spkadd(batch), exact_values=exact)
+        for mode in (1, 2):
+            got = run_gpu(batch, _opts(wave_merge=merge, accum_mode=mode))
+            assert_matches(batch, got, oracle.spkadd(batch), exact_values=exact)
+
+
 def test_degenerate_hash():
     note("degenerate_hash")
     batch = workloads.er(3000, 200, 5, 30.0, seed=8, values="int32f")
