@@ -21,69 +21,69 @@
 
 namespace spk {
 
-// Entry addresses of one unit.  Every non-empty segment i writes its id at byte
-// P[i] of a mark array; a running max-scan over the marks (DPP, carried from one
-// chunk of 64 entries to the next) then gives each entry its segment.  Lanes past
-// the end re-read the unit's last entry, so no load is masked off.
+// Entry addresses of one unit.  The non-empty segments (inputs with entries in the
+// column) are numbered in order, and each sets the bit of its start position in a
+// 64 E-bit start mask.  The segment of position p is (#starts at positions <= p)
+// - 1: per chunk of 64 positions, the starts of earlier chunks (a scalar count)
+// plus mbcnt over the chunk's mask word.  Lanes past the end take the unit's last
+// entry (every unit has u > 0), so no load is masked off.
 template <int E, bool NUM, typename V>
 __device__ __forceinline__ void issue_unit_loads(const KArgs& a, unsigned char* base, const long long* adj,
                                                  const long long* adjv, int u, int (&rows)[E], V (&vals)[E]) {
   const int lane = lane_id();
-  signed char* marks = (signed char*)(base + a.off_mark);
-  int seg[E];
-  int carry = 0;
-#pragma unroll
-  for (int t = 0; t < E; ++t) {
-    const int mk = marks[64 * t + lane];
-    const int sc = max(wave_scan_max(mk), carry);
-    carry = readlane(sc, 63);
-    seg[t] = sc;
-  }
+  const unsigned long long* sb = reinterpret_cast<const unsigned long long*>(base + a.off_mark);
   long long ar[E], av[E];
+  int before = -1;  // starts in earlier chunks, minus one
 #pragma unroll
   for (int t = 0; t < E; ++t) {
-    ar[t] = adj[seg[t]];
-    if (NUM) av[t] = adjv[seg[t]];
+    const unsigned long long w = sb[t];
+    // (the builtin returns int: go through unsigned so the low word is not sign-extended)
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(w >> 32));
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)w);
+    const unsigned long long S = ((unsigned long long)hi << 32) | (unsigned long long)lo;
+    const int seg = before + (int)(S & 1ull) + mbcnt(S >> 1);
+    before += __popcll(S);
+    ar[t] = adj[seg];
+    if (NUM) av[t] = adjv[seg];
   }
-  const long long dummy = (long long)a.dummy;
 #pragma unroll
   for (int t = 0; t < E; ++t) {
     const int e = min(lane + 64 * t, u - 1);
-    rows[t] = gload<int>(u > 0 ? ar[t] + 4LL * e : dummy);
-    if (NUM) vals[t] = gload<V>(u > 0 ? av[t] + (long long)sizeof(V) * e : dummy);
+    rows[t] = gload<int>(ar[t] + 4LL * e);
+    if (NUM) vals[t] = gload<V>(av[t] + (long long)sizeof(V) * e);
   }
 }
 
 // Column pointers of unit column j: lane i < k reads colptr_i[j], colptr_i[j+1];
 // lanes 0 and 1 also read colptr(B)[j], colptr(B)[j+1] for the numeric pass.
-// Lanes >= k hold the pointer of input k-1 and so repeat lane k-1's reads; a null
-// unit (j < 0) reads column 0 and is given zero length by build_unit_meta.
+// Lanes >= k hold the pointer of input k-1 and so repeat lane k-1's reads.
 template <bool NUM>
 __device__ __forceinline__ void issue_meta_loads(const KArgs& a, long long cpp, int j, int& s, int& e, int& cc) {
   const int lane = lane_id();
-  const int jj = j < 0 ? 0 : j;
-  s = gload<int>(cpp + 4LL * jj);
-  e = gload<int>(cpp + 4LL * (jj + 1));
-  if (NUM) cc = gload<int>((long long)(a.colptr_c + jj + (lane & 1)));
+  s = gload<int>(cpp + 4LL * j);
+  e = gload<int>(cpp + 4LL * (j + 1));
+  if (NUM) cc = gload<int>((long long)(a.colptr_c + j + (lane & 1)));
 }
 
-// Segment table of a unit from its column pointers; returns u.
+// Segment table of a unit from its column pointers: the base pointers of the
+// non-empty segments, shifted so that entry index (position in the unit) addresses
+// them, in segment order, and the start mask.  Returns u.
 template <int E, bool NUM, typename V>
 __device__ __forceinline__ int build_unit_meta(const KArgs& a, unsigned char* base, long long rip, long long vap,
-                                               int s, int e, long long* adj, long long* adjv, bool null_unit) {
+                                               int s, int e, long long* adj, long long* adjv) {
   const int lane = lane_id();
-  const int len = (lane < a.k && !null_unit) ? e - s : 0;
+  const int len = lane < a.k ? e - s : 0;
   const int incl = wave_scan_add(len);
   const int ex = incl - len;
-  if (lane < a.k) {
-    adj[lane] = rip + 4LL * (s - ex);
-    if (NUM) adjv[lane] = vap + (long long)sizeof(V) * (s - ex);
+  const int ord = mbcnt(ballot(len > 0));
+  if (len > 0) {
+    adj[ord] = rip + 4LL * (s - ex);
+    if (NUM) adjv[ord] = vap + (long long)sizeof(V) * (s - ex);
   }
-  // marks: -1 everywhere (64 E bytes, 16 per lane), then segment ids at the starts
-  signed char* marks = (signed char*)(base + a.off_mark);
-  if (lane < 4 * E) reinterpret_cast<int4*>(marks)[lane] = make_int4(-1, -1, -1, -1);
+  unsigned* sb = reinterpret_cast<unsigned*>(base + a.off_mark);
+  if (lane < 2 * E) sb[lane] = 0u;
   wave_sync();
-  if (len > 0) marks[ex] = (signed char)lane;
+  if (len > 0) atomicOr(&sb[ex >> 5], 1u << (ex & 31));
   return readlane(incl, 63);
 }
 
@@ -110,6 +110,26 @@ __device__ __forceinline__ void lds_add_cas(V* p, V v) {
       if (prev == old) break;
       old = prev;
     }
+  }
+}
+
+// Coalesced write-out of an output column staged in LDS (rows br[0..c), values
+// bv[0..c), rows ascending) at offset o0 of rowidx(B) / values(B).  Lanes past the
+// end repeat the last entry's store (same address, same value).  With c == 0 (a
+// replayed or failed unit) every lane stores into the write sink instead.  The base
+// pointers are the same for the whole wavefront, so only the offsets are per lane.
+template <int E, typename V>
+__device__ __forceinline__ void write_column(const KArgs& a, int o0, int c, const int* br, const V* bv) {
+  const int lane = lane_id();
+  const bool live = c > 0;
+  int* ob = live ? a.out_r + o0 : reinterpret_cast<int*>((char*)a.dummy + 2048);
+  V* ov = live ? (V*)a.out_v + o0 : reinterpret_cast<V*>((char*)a.dummy + 2048 + 64);
+  const int last = live ? c - 1 : 0;
+#pragma unroll
+  for (int t = 0; t < E; ++t) {
+    const int q = min(64 * t + lane, last);
+    gstore<int>((long long)(ob + q), br[q]);
+    gstore<V>((long long)(ov + q), bv[q]);
   }
 }
 
@@ -158,7 +178,7 @@ __device__ __forceinline__ int insert_batch(int* K, V* Vt, int TS, int mode, int
 // write-out.  The key and value arrays have 64 extra sink slots after ts_max; lanes
 // without an entry write there, so no store is predicated.
 template <int E, typename V>
-__device__ __forceinline__ void num_unit(const KArgs& a, unsigned char* base, int u, int cnt, int o0,
+__device__ __forceinline__ void num_unit(const KArgs& a, unsigned char* base, int u, int cnt, int o0, bool live,
                                          const int (&rows)[E], const V (&vals)[E]) {
   constexpr int NCH = 2 * E;  // 64-slot table chunks at load factor 1/2
   constexpr int RANK_UNROLL = 4;
@@ -199,6 +219,7 @@ __device__ __forceinline__ void num_unit(const KArgs& a, unsigned char* base, in
     if (lane == 0) atomicOr(a.err, ERR_COUNT);
     nc = 0;  // write nothing for this unit
   }
+  if (!live) nc = 0;  // a replayed unit writes nothing
   mn = wave_total_min(mn);
   mx = wave_total_max(mx);
   const int bits = mx >= mn ? ceil_log2(mx - mn + 1) : 0;
@@ -258,17 +279,7 @@ __device__ __forceinline__ void num_unit(const KArgs& a, unsigned char* base, in
     Vt[dst] = val;
   }
   wave_sync();
-  // coalesced write-out; lanes past the end repeat the last entry's store (same
-  // address, same value); an empty unit writes into the dummy sink
-  const long long dst = (long long)(a.out_r + o0), dsv = (long long)((V*)a.out_v + o0);
-  const long long dmy = (long long)a.dummy + 2048 + 8LL * lane;  // write sink, never read
-#pragma unroll
-  for (int c = 0; c < E; ++c) {
-    const int p = min(64 * c + lane, nc - 1);
-    const int q = p < 0 ? 0 : p;
-    gstore<int>(nc > 0 ? dst + 4LL * q : dmy, K[q]);
-    gstore<V>(nc > 0 ? dsv + (long long)sizeof(V) * q : dmy, Vt[q]);
-  }
+  write_column<E, V>(a, o0, nc, K, Vt);
 }
 
 // ---------------------------------------------------------------------------
@@ -282,29 +293,31 @@ __device__ __forceinline__ void num_unit(const KArgs& a, unsigned char* base, in
 // adds with compare-and-swap.
 // The bitmap holds bm_nq x 256 words (bm_nq x 8192 rows).
 // ---------------------------------------------------------------------------
+// Symbolic: OR the rows in; an OR that finds its bit clear counts a new row.  The
+// bitmap is all zero on entry (cleared at the start of the run) and is left all
+// zero: the words the unit touched are cleared again.
 template <int E>
 __device__ __forceinline__ int bm_sym_unit(const KArgs& a, unsigned char* base, int u, const int (&rows)[E]) {
   const int lane = lane_id();
-  uint4* bm4 = reinterpret_cast<uint4*>(base + a.off_bm);
-  unsigned* bm = reinterpret_cast<unsigned*>(bm4);
-  for (int q = 0; q < a.bm_nq; ++q) bm4[q * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
-  wave_sync();
-  // lanes past the end hold a copy of the unit's last row (or row 0 in a null unit)
-  // and OR nothing
+  unsigned* bm = reinterpret_cast<unsigned*>(base + a.off_bm);
+  int newc = 0;
+  // lanes past the end hold a copy of the unit's last row and OR nothing
 #pragma unroll
-  for (int t = 0; t < E; ++t)
-    atomicOr(&bm[rows[t] >> 5], lane + 64 * t < u ? 1u << (rows[t] & 31) : 0u);
-  wave_sync();
-  int c = 0;
-  for (int q = 0; q < a.bm_nq; ++q) {
-    const uint4 x = bm4[q * 64 + lane];
-    c += __popc(x.x) + __popc(x.y) + __popc(x.z) + __popc(x.w);
+  for (int t = 0; t < E; ++t) {
+    const bool in = lane + 64 * t < u;
+    const unsigned bit = in ? 1u << (rows[t] & 31) : 0u;
+    const unsigned old = atomicOr(&bm[rows[t] >> 5], bit);
+    newc += (in && (old & bit) == 0) ? 1 : 0;
   }
-  return wave_total_add(c);
+  wave_sync();
+#pragma unroll
+  for (int t = 0; t < E; ++t) bm[rows[t] >> 5] = 0u;
+  wave_sync();
+  return wave_total_add(newc);
 }
 
 template <int E, typename V>
-__device__ __forceinline__ void bm_num_unit(const KArgs& a, unsigned char* base, int u, int cnt, int o0,
+__device__ __forceinline__ void bm_num_unit(const KArgs& a, unsigned char* base, int u, int cnt, int o0, bool live,
                                             const int (&rows)[E], const V (&vals)[E]) {
   const int lane = lane_id();
   uint4* bm4 = reinterpret_cast<uint4*>(base + a.off_bm);
@@ -342,6 +355,7 @@ __device__ __forceinline__ void bm_num_unit(const KArgs& a, unsigned char* base,
     if (lane == 0) atomicOr(a.err, ERR_COUNT);
     c = 0;
   }
+  if (!live) c = 0;  // a replayed unit writes nothing
   wave_sync();
   // rank(row) = set bits below it = output position; the first entry of a row puts
   // the row and its value there, later entries of the row add their values
@@ -367,17 +381,7 @@ __device__ __forceinline__ void bm_num_unit(const KArgs& a, unsigned char* base,
   for (int t = 0; t < E; ++t)
     if (lane + 64 * t < u && !first[t]) lds_add_cas<V>(&bv[rk[t]], vals[t]);
   wave_sync();
-  // coalesced write-out of B(:,j), rows ascending; lanes past the end repeat the last
-  // entry's store, and an empty (or failed) unit writes into the dummy sink
-  const long long dst = (long long)(a.out_r + o0), dsv = (long long)((V*)a.out_v + o0);
-  const long long dmy = (long long)a.dummy + 2048 + 8LL * lane;
-#pragma unroll
-  for (int t = 0; t < E; ++t) {
-    const int p = min(64 * t + lane, c - 1);
-    const int q = p < 0 ? 0 : p;
-    gstore<int>(c > 0 ? dst + 4LL * q : dmy, br[q]);
-    gstore<V>(c > 0 ? dsv + (long long)sizeof(V) * q : dmy, bv[q]);
-  }
+  write_column<E, V>(a, o0, c, br, bv);
 }
 
 // Marks the entry registers of a unit as needed here.  Called before the next
@@ -424,8 +428,9 @@ struct UnitRegs {
 
 // One pipeline step: finish the metadata of unit t+1, start loads for units t+2
 // (pointers) and t+1 (entries), then process unit t.
-// Units t >= nu are null units (no entries, no output): every step runs the same
-// instruction sequence, so the compiler keeps the next unit's loads in flight.
+// Steps t >= nu (the loop runs an even count) replay the wavefront's last unit with
+// its output sent to the write sink: every step runs the same instruction sequence
+// on a real column, so the compiler keeps the next unit's loads in flight.
 template <int E, bool NUM, typename V, bool BM>
 __device__ __forceinline__ void pipe_step(const KArgs& a, unsigned char* base, int t, int nu, int ucol,
                                           long long cpp, long long rip, long long vap, int& ms, int& me, int& mc,
@@ -436,24 +441,24 @@ __device__ __forceinline__ void pipe_step(const KArgs& a, unsigned char* base, i
     const int b = (t + 1) & 1;
     long long* adj = (long long*)(base + a.off_adj) + 64 * b;
     long long* adjv = (long long*)(base + a.off_adjv) + 64 * b;
-    nxt.j = t + 1 < nu ? readlane(ucol, (t + 1) & 63) : -1;
-    nxt.u = build_unit_meta<E, NUM, V>(a, base, rip, vap, ms, me, adj, adjv, nxt.j < 0);
+    nxt.j = t + 1 < nu ? readlane(ucol, t + 1) : -1;  // -1: a replay, no output
+    nxt.u = build_unit_meta<E, NUM, V>(a, base, rip, vap, ms, me, adj, adjv);
     if (NUM) {
       nxt.o0 = readlane(mc, 0);
-      nxt.cnt = nxt.j < 0 ? 0 : readlane(mc, 1) - nxt.o0;
+      nxt.cnt = readlane(mc, 1) - nxt.o0;
     }
-    issue_meta_loads<NUM>(a, cpp, t + 2 < nu ? readlane(ucol, (t + 2) & 63) : -1, ms, me, mc);
+    issue_meta_loads<NUM>(a, cpp, readlane(ucol, min(t + 2, nu - 1)), ms, me, mc);
     wave_sync();
     issue_unit_loads<E, NUM, V>(a, base, adj, adjv, nxt.u, nxt.rows, nxt.vals);
   }
   if constexpr (NUM && BM) {
-    bm_num_unit<E, V>(a, base, cur.u, cur.cnt, cur.o0, cur.rows, cur.vals);
+    bm_num_unit<E, V>(a, base, cur.u, cur.cnt, cur.o0, cur.j >= 0, cur.rows, cur.vals);
   } else if constexpr (NUM) {
-    num_unit<E, V>(a, base, cur.u, cur.cnt, cur.o0, cur.rows, cur.vals);
+    num_unit<E, V>(a, base, cur.u, cur.cnt, cur.o0, cur.j >= 0, cur.rows, cur.vals);
   } else if constexpr (BM) {
     const int cnt = bm_sym_unit<E>(a, base, cur.u, cur.rows);
     // one unconditional store instruction: lane 0 writes the count, the other
-    // lanes (and null units) write into their write-sink slots
+    // lanes (and replayed units) write into their write-sink slots
     const long long dmy = (long long)a.dummy + 2048 + 8LL * lane;
     gstore<int>(lane == 0 && cur.j >= 0 ? (long long)(a.colcnt + cur.j) : dmy, cnt);
     wave_sync();
@@ -497,15 +502,20 @@ __global__ __launch_bounds__(256) void k_wave_pipe(KArgs a, const int* __restric
   {
     long long* adj = (long long*)(base + a.off_adj);
     long long* adjv = (long long*)(base + a.off_adjv);
-    A.u = build_unit_meta<E, NUM, V>(a, base, rip, vap, ms, me, adj, adjv, false);
+    A.u = build_unit_meta<E, NUM, V>(a, base, rip, vap, ms, me, adj, adjv);
     A.j = readlane(ucol, 0);
     if (NUM) {
       A.o0 = readlane(mc, 0);
       A.cnt = readlane(mc, 1) - A.o0;
     }
-    issue_meta_loads<NUM>(a, cpp, nu > 1 ? readlane(ucol, 1) : -1, ms, me, mc);
+    issue_meta_loads<NUM>(a, cpp, readlane(ucol, min(1, nu - 1)), ms, me, mc);
     wave_sync();
     issue_unit_loads<E, NUM, V>(a, base, adj, adjv, A.u, A.rows, A.vals);
+  }
+  if constexpr (!NUM && BM) {  // the symbolic bitmap starts all zero and stays so
+    uint4* bm4 = reinterpret_cast<uint4*>(base + a.off_bm);
+    for (int q = 0; q < a.bm_nq; ++q) bm4[q * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
+    wave_sync();
   }
   prime_stores<E, NUM, V>(a);
   const int steps = (nu + 1) & ~1;
@@ -538,8 +548,8 @@ void lds_layout_pipe(int bin, bool numeric, int vbytes, int ts_max, int bm_nq, K
   int off = bm_nq > 0 ? bm_bytes : hash_bytes;
   off = (off + 15) & ~15;
   a.off_hist = ((ts_max + 64) * 4 + (ts_max + 64) * vbytes + 15) & ~15;  // used by the hash layout only
-  a.off_mark = off;
-  off += 64 * E;
+  a.off_mark = off;  // start mask: E 64-bit words
+  off += 8 * E;
   off = (off + 15) & ~15;
   a.off_P = off;
   a.off_adj = off;
