@@ -37,7 +37,9 @@ enum : int {
 // Threads of the workgroup bins.
 constexpr int G1_THREADS = 256;
 constexpr int G2_THREADS = 512;
-constexpr int WAVES_PER_BLOCK = 4;   // wave bins: columns per 256-thread block
+constexpr int WAVES_PER_BLOCK = 4;   // wave bins (hash kernels): columns per 256-thread block
+constexpr int PIPE_WAVES_PER_BLOCK = 4;  // pipelined wave kernels: the wavefronts of a workgroup share
+                                         // the CU L1 for neighbouring columns
 constexpr int PLAN_THREADS = 256;
 
 struct PlanParams {

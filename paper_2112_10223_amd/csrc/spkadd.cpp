@@ -355,8 +355,8 @@ spkadd_status check_lds(spkadd_plan_s* p) {
     if (cnt == 0) continue;
     for (int numeric = 0; numeric < 2; ++numeric) {
       KArgs a{};
-      layout_bin(p, b, numeric != 0, a);
-      const long long bytes = (long long)a.slice_bytes * bin_units_per_block(b);
+      const bool pipe = layout_bin(p, b, numeric != 0, a);
+      const long long bytes = (long long)a.slice_bytes * (pipe ? PIPE_WAVES_PER_BLOCK : bin_units_per_block(b));
       if (bytes > lmax)
         return set_error(SPKADD_ERR_UNSUPPORTED,
                          "bin %d needs %lld bytes of LDS (k=%d, table %d slots); the device has %d", b, bytes, p->k,
@@ -572,11 +572,12 @@ hipError_t launch_bin(spkadd_plan_s* p, int b, bool numeric, KArgs& a, hipStream
   const bool f64 = p->dtype == SPKADD_F64;
   const int* list = b == BIN_WIN ? nullptr : p->d_list + p->binoff[b];
   if (layout_bin(p, b, numeric, a)) {
-    const int block_lds = a.slice_bytes * WAVES_PER_BLOCK;
+    // resident wavefronts per CU: LDS-bound, at most 16 (four per SIMD)
+    const int block_lds = a.slice_bytes * PIPE_WAVES_PER_BLOCK;
     int bpc = max_lds_bytes() / block_lds;
-    if (bpc > 8) bpc = 8;
+    if (bpc > 16 / PIPE_WAVES_PER_BLOCK) bpc = 16 / PIPE_WAVES_PER_BLOCK;
     if (bpc < 1) bpc = 1;
-    const long long resident = (long long)p->n_cu * bpc * WAVES_PER_BLOCK;
+    const long long resident = (long long)p->n_cu * bpc * PIPE_WAVES_PER_BLOCK;
     long long upw = (cnt + resident - 1) / resident;
     a.upw = (int)(upw < 1 ? 1 : upw > 64 ? 64 : upw);
     return launch_wave_pipe(b, numeric, f64, a, list, cnt, s);

@@ -438,9 +438,10 @@ __device__ __forceinline__ void pipe_step(const KArgs& a, unsigned char* base, i
   const int lane = lane_id();
   require_loaded<E, NUM, V>(cur.rows, cur.vals);
   {
-    const int b = (t + 1) & 1;
-    long long* adj = (long long*)(base + a.off_adj) + 64 * b;
-    long long* adjv = (long long*)(base + a.off_adjv) + 64 * b;
+    // one segment table: a unit's pointers are read into registers in the step
+    // that writes them
+    long long* adj = (long long*)(base + a.off_adj);
+    long long* adjv = (long long*)(base + a.off_adjv);
     nxt.j = t + 1 < nu ? readlane(ucol, t + 1) : -1;  // -1: a replay, no output
     nxt.u = build_unit_meta<E, NUM, V>(a, base, rip, vap, ms, me, adj, adjv);
     if (NUM) {
@@ -477,15 +478,16 @@ __device__ __forceinline__ void pipe_step(const KArgs& a, unsigned char* base, i
 }
 
 template <int E, bool NUM, typename V, bool BM>
-__global__ __launch_bounds__(256) void k_wave_pipe(KArgs a, const int* __restrict__ list, int nunits) {
+__global__ __launch_bounds__(64 * PIPE_WAVES_PER_BLOCK) void k_wave_pipe(KArgs a, const int* __restrict__ list,
+                                                                        int nunits) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = lane_id(), w = threadIdx.x >> 6;
   // Units are dealt out with stride G (all wavefronts of the launch): at any time
   // the wavefronts of one XCD (consecutive gw after the remap) work on neighbouring
   // columns, whose input rows share cache lines, instead of each wavefront walking a
   // column range of its own (too many partly used lines for the L2).
-  const int G = (int)gridDim.x * WAVES_PER_BLOCK;
-  const int gw = xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + w;
+  const int G = (int)gridDim.x * PIPE_WAVES_PER_BLOCK;
+  const int gw = xcd_remap(blockIdx.x, gridDim.x) * PIPE_WAVES_PER_BLOCK + w;
   if (gw >= nunits) return;  // no block-wide barriers in this kernel
   const int nu = (nunits - gw + G - 1) / G;  // <= upw <= 64
   unsigned char* base = smem + w * a.slice_bytes;
@@ -553,9 +555,9 @@ void lds_layout_pipe(int bin, bool numeric, int vbytes, int ts_max, int bm_nq, K
   off = (off + 15) & ~15;
   a.off_P = off;
   a.off_adj = off;
-  off += 2 * 64 * 8;
+  off += 64 * 8;
   a.off_adjv = off;
-  if (numeric) off += 2 * 64 * 8;
+  if (numeric) off += 64 * 8;
   a.slice_bytes = (off + 15) & ~15;
   a.ts_max = ts_max;
 }
@@ -563,16 +565,16 @@ void lds_layout_pipe(int bin, bool numeric, int vbytes, int ts_max, int bm_nq, K
 template <int E, bool NUM, typename V>
 static void launch_pipe_e(const KArgs& a, const int* list, int n, unsigned blocks, size_t lds, hipStream_t s) {
   if (a.bm_nq > 0)
-    k_wave_pipe<E, NUM, V, true><<<blocks, 256, lds, s>>>(a, list, n);
+    k_wave_pipe<E, NUM, V, true><<<blocks, 64 * PIPE_WAVES_PER_BLOCK, lds, s>>>(a, list, n);
   else
-    k_wave_pipe<E, NUM, V, false><<<blocks, 256, lds, s>>>(a, list, n);
+    k_wave_pipe<E, NUM, V, false><<<blocks, 64 * PIPE_WAVES_PER_BLOCK, lds, s>>>(a, list, n);
 }
 
 template <bool NUM, typename V>
 static hipError_t launch_pipe_t(int bin, const KArgs& a, const int* list, int n, hipStream_t s) {
   const int waves = (n + a.upw - 1) / a.upw;
-  const unsigned blocks = (unsigned)((waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK);
-  const size_t lds = (size_t)a.slice_bytes * WAVES_PER_BLOCK;
+  const unsigned blocks = (unsigned)((waves + PIPE_WAVES_PER_BLOCK - 1) / PIPE_WAVES_PER_BLOCK);
+  const size_t lds = (size_t)a.slice_bytes * PIPE_WAVES_PER_BLOCK;
   switch (bin) {
     case BIN_W1: launch_pipe_e<1, NUM, V>(a, list, n, blocks, lds, s); break;
     case BIN_W2: launch_pipe_e<2, NUM, V>(a, list, n, blocks, lds, s); break;
