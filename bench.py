@@ -84,15 +84,17 @@ def source_sha() -> str:
 
 
 def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
-    or None when there is none or the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (profiles/traffic_<kernel>_<workload>.md), or None when there is none or the
+    kernel sources changed since the counters were taken."""
+    from paper_2112_10223_amd import profiling
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
+    rec = profiling.read_traffic_summary(path)
     if rec.get("source_sha") != source_sha():
         return None
-    return rec.get("traffic_bytes_per_launch")
+    return int(rec["traffic_bytes_per_launch"])
 
 
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 3) -> None:
@@ -103,7 +105,7 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 3) -> None:
     for _ in range(reps):
         torch.neg(src, out=dst)  # one elementwise kernel: reads nbytes, writes nbytes
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes": nbytes, "reps": reps}))
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps, "source_sha": source_sha()}))
 
 
 def cpu_baseline(batch, max_cols: int | None = None):
