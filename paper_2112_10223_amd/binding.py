@@ -20,6 +20,7 @@ SPKADD_F32, SPKADD_F64 = 0, 1
 SPKADD_FLAG_VALIDATE, SPKADD_FLAG_TRACE, SPKADD_FLAG_TRACE_NUMERIC = 1, 2, 4
 SPKADD_BIN_AUTO, SPKADD_BIN_WAVE, SPKADD_BIN_WG, SPKADD_BIN_WINDOW = -1, 0, 1, 2
 SPKADD_ACCUM_AUTO, SPKADD_ACCUM_HASH, SPKADD_ACCUM_BITMAP = 0, 1, 2
+SPKADD_REQ_OK, SPKADD_REQ_TOO_LARGE, SPKADD_REQ_CAPACITY = 0, 1, 2
 
 
 class SpkaddError(RuntimeError):
@@ -41,6 +42,18 @@ class Stats(ctypes.Structure):
                 ("n_wave_cols", ctypes.c_int32), ("n_wg_cols", ctypes.c_int32), ("n_window_cols", ctypes.c_int32),
                 ("n_windows", ctypes.c_int32), ("window_levels", ctypes.c_int32), ("window_cap", ctypes.c_int32),
                 ("wave_max", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("colptr", ctypes.c_void_p), ("rowidx", ctypes.c_void_p), ("values", ctypes.c_void_p),
+                ("colptr_c", ctypes.c_void_p), ("rowidx_c", ctypes.c_void_p), ("values_c", ctypes.c_void_p),
+                ("cap_c", ctypes.c_int64)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("graphs_captured", ctypes.c_int32), ("graph_replays", ctypes.c_int32),
+                ("kernels_per_run", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def declared_functions():
@@ -87,6 +100,16 @@ def lib():
         L.spkadd_trace_get.restype = ctypes.c_int
         L.spkadd_trace_reset.argtypes = [P]
         L.spkadd_trace_reset.restype = ctypes.c_int
+        L.spkadd_batch_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, I32, I64, I64, ctypes.POINTER(Opts)]
+        L.spkadd_batch_create.restype = ctypes.c_int
+        L.spkadd_batch_run.argtypes = [P, ctypes.POINTER(Request), I32, I32, P]
+        L.spkadd_batch_run.restype = ctypes.c_int
+        L.spkadd_batch_results.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I32)]
+        L.spkadd_batch_results.restype = ctypes.c_int
+        L.spkadd_batch_get_info.argtypes = [P, ctypes.POINTER(BatchInfo)]
+        L.spkadd_batch_get_info.restype = ctypes.c_int
+        L.spkadd_batch_destroy.argtypes = [P]
+        L.spkadd_batch_destroy.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -111,11 +134,11 @@ class PtrArray:
     non_null=True, pointers of empty tensors (which torch reports as 0) are replaced
     by another input's pointer; they are never read through."""
 
-    def __init__(self, tensors, non_null: bool = False):
+    def __init__(self, tensors, non_null: bool = False, fallback: int = 0):
         self.tensors = list(tensors)
         ptrs = [t.data_ptr() if t is not None else 0 for t in self.tensors]
         if non_null:
-            fill = next((q for q in ptrs if q), 0)
+            fill = next((q for q in ptrs if q), fallback)
             ptrs = [q or fill for q in ptrs]
         self.arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
 
@@ -228,3 +251,60 @@ def spkadd(m, colptrs, rowidxs, values, opts: Opts | None = None, stream=None):
     finally:
         plan.free()
     return colptr_c, rowidx_c, values_c
+
+
+class Batch:
+    """Owning handle of an spkadd_batch_t (include/spkadd_batch.h).
+
+    run() takes a list of requests, each a dict with m, colptrs, rowidxs, values (k
+    device tensors or PtrArray each), colptr_c, rowidx_c, values_c (device tensors)
+    and cap_c.  The pointer arrays are kept alive until the next run."""
+
+    def __init__(self, dtype, max_requests, max_columns, max_inputs, opts: Opts | None = None):
+        h = ctypes.c_void_p()
+        _check(lib().spkadd_batch_create(ctypes.byref(h), dtype, max_requests, max_columns, max_inputs,
+                                         ctypes.byref(opts) if opts is not None else None))
+        self.handle = h
+        self._keep = []
+        self.nreq = 0
+
+    def run(self, requests, use_graph: bool = True, stream=None) -> None:
+        arr = (Request * len(requests))()
+        keep = []
+        for r, q in enumerate(requests):
+            # inputs without entries still need a device pointer (never read through)
+            fb = q["colptr_c"].data_ptr()
+            cps = q["colptrs"] if isinstance(q["colptrs"], PtrArray) else PtrArray(q["colptrs"], True, fb)
+            ris = q["rowidxs"] if isinstance(q["rowidxs"], PtrArray) else PtrArray(q["rowidxs"], True, fb)
+            vas = q["values"] if isinstance(q["values"], PtrArray) else PtrArray(q["values"], True, fb)
+            keep += [cps, ris, vas, q["colptr_c"], q["rowidx_c"], q["values_c"]]
+            n = q["colptr_c"].shape[0] - 1
+            arr[r] = Request(q["m"], n, len(cps), ctypes.cast(cps.arr, ctypes.c_void_p).value,
+                             ctypes.cast(ris.arr, ctypes.c_void_p).value, ctypes.cast(vas.arr, ctypes.c_void_p).value,
+                             q["colptr_c"].data_ptr(), q["rowidx_c"].data_ptr() or None,
+                             q["values_c"].data_ptr() or None, int(q["cap_c"]))
+        _check(lib().spkadd_batch_run(self.handle, arr, len(requests), 1 if use_graph else 0, _stream_ptr(stream)))
+        self._keep = keep
+        self.nreq = len(requests)
+
+    def results(self):
+        nnz = (ctypes.c_int64 * self.nreq)()
+        st = (ctypes.c_int32 * self.nreq)()
+        _check(lib().spkadd_batch_results(self.handle, nnz, st))
+        return list(nnz), list(st)
+
+    def info(self) -> dict:
+        i = BatchInfo()
+        _check(lib().spkadd_batch_get_info(self.handle, ctypes.byref(i)))
+        return {name: getattr(i, name) for name, _ in BatchInfo._fields_}
+
+    def close(self):
+        if self.handle:
+            lib().spkadd_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

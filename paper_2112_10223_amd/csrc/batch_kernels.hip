@@ -1,0 +1,285 @@
+// Kernels of the batched launch (include/spkadd_batch.h): the columns of every
+// request form one global worklist.  Global column g belongs to request r with
+// col_base(r) <= g < col_base(r) + n_r.
+//
+//   k_batch_init    clears the per-request outcome and the counters (a kernel, so
+//                   the run can be captured in a graph)
+//   k_batch_bounds  u_j of every column (Section III-A) and its slot: empty, too
+//                   large for a wavefront (u_j > 1024), or (wave bin E, accumulator)
+//   k_batch_slot_scan / k_batch_scatter  counting sort of the columns by slot;
+//                   inside a slot the columns keep their global order, so each
+//                   request's columns are contiguous
+//   k_batch_wave    persistent wave kernels, one launch per (E, accumulator): chunks
+//                   of the slot's list, split into runs of one request, each run
+//                   through the same per-wavefront pipeline as the plain launch
+//   k_batch_scan    one workgroup per request: colptr(B_r), nnz(B_r), capacity check
+#include <climits>
+
+#include "batch_internal.h"
+#include "wave_device.h"
+
+namespace spk {
+
+// Wavefront bins of the batch (same E menu as the plain launch).
+__device__ __forceinline__ int batch_wave_index(int u) {
+  const int e = (u + 63) >> 6;
+  return e <= 1 ? 0 : e <= 2 ? 1 : e <= 3 ? 2 : e <= 4 ? 3 : e <= 5 ? 4 : e <= 6 ? 5 : e <= 8 ? 6 : e <= 10 ? 7
+       : e <= 12 ? 8 : 9;
+}
+
+__device__ __forceinline__ int request_of(const BatchReq* __restrict__ reqs, int nreq, int g) {
+  int lo = 0, hi = nreq - 1;  // last r with col_base(r) <= g
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (reqs[mid].col_base <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_batch_init(BatchArgs b) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  for (int r = t; r < b.max_reqs; r += gridDim.x * 256) {
+    b.status[r] = 0;
+    b.nnz[r] = 0;
+  }
+  if (t < 1024) reinterpret_cast<unsigned*>(const_cast<void*>(b.dummy))[t] = 0u;
+  if (t == 0) *b.err = 0;
+}
+
+// Block c handles columns [c * b.chunk, (c + 1) * b.chunk) in 256-column steps.
+__global__ __launch_bounds__(256) void k_batch_bounds(BatchArgs b) {
+  __shared__ int cnt[BSLOTS];
+  __shared__ int wh[4][BSLOTS];
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  const int nreq = b.hdr->nreq, total = b.hdr->total_cols;
+  if (threadIdx.x < BSLOTS) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int c0 = blockIdx.x * b.chunk;
+  for (int step = 0; step < b.chunk; step += 256) {
+    const int g = c0 + step + threadIdx.x;
+    int slot = -1;
+    if (g < total) {
+      const int r = request_of(b.reqs, nreq, g);
+      const BatchReq& q = b.reqs[r];
+      const int j = g - q.col_base;
+      long long u = 0;
+      for (int i = 0; i < q.k; ++i) {
+        const int* c = q.cp[i];
+        u += (long long)(c[j + 1] - c[j]);
+      }
+      b.req_of[g] = r;
+      b.colcnt[g] = 0;
+      if (u <= 0) {
+        slot = BSLOT_EMPTY;
+      } else if (u > 1024) {
+        slot = BSLOT_LARGE;
+        atomicOr(&b.status[r], REQ_TOO_LARGE);
+      } else {
+        const int wi = batch_wave_index((int)u);
+        const int E = wave_bin_E(BIN_W1 + wi);
+        const bool bm = b.accum_mode != 1 && q.nq > 0 &&
+                        (b.accum_mode == 2 || (float)q.nq <= b.bitmap_ratio * (float)E);
+        slot = BSLOT_WAVE + 2 * wi + (bm ? 1 : 0);
+      }
+      b.slot[g] = (unsigned char)slot;
+    }
+    for (int s = 0; s < BSLOTS; ++s) {
+      const uint64_t mk = ballot(slot == s);
+      if (lane == 0) wh[w][s] = __popcll(mk);
+    }
+    __syncthreads();
+    if (threadIdx.x < BSLOTS) cnt[threadIdx.x] += wh[0][threadIdx.x] + wh[1][threadIdx.x] + wh[2][threadIdx.x] +
+                                                   wh[3][threadIdx.x];
+    __syncthreads();
+  }
+  if (threadIdx.x < BSLOTS) b.hist[blockIdx.x * BSLOTS + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// One block of 1024 threads; wavefront w scans slots w, w + 16, ... over the bounds
+// blocks.
+__global__ __launch_bounds__(1024) void k_batch_slot_scan(BatchArgs b) {
+  __shared__ int tot[BSLOTS];
+  const int lane = lane_id();
+  for (int s = threadIdx.x >> 6; s < BSLOTS; s += 16) {
+    int carry = 0;
+    for (int base = 0; base < b.nblk; base += 64) {
+      const int t = base + lane;
+      const int v = t < b.nblk ? b.hist[t * BSLOTS + s] : 0;
+      const int incl = wave_scan_add(v);
+      if (t < b.nblk) b.hist[t * BSLOTS + s] = carry + incl - v;
+      carry += readlane(incl, 63);
+    }
+    if (lane == 0) tot[s] = carry;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int x = 0; x < BSLOTS; ++x) {
+      b.slotoff[x] = acc;
+      b.slotoff[BSLOTS + 1 + x] = tot[x];
+      acc += tot[x];
+    }
+    b.slotoff[BSLOTS] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_batch_scatter(BatchArgs b) {
+  __shared__ int run[BSLOTS];
+  __shared__ int wc[4][BSLOTS];
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  const int total = b.hdr->total_cols;
+  if (threadIdx.x < BSLOTS) run[threadIdx.x] = b.slotoff[threadIdx.x] + b.hist[blockIdx.x * BSLOTS + threadIdx.x];
+  __syncthreads();
+  const int c0 = blockIdx.x * b.chunk;
+  for (int step = 0; step < b.chunk; step += 256) {
+    const int g = c0 + step + threadIdx.x;
+    const int slot = g < total ? (int)b.slot[g] : -1;
+    int rank = 0;
+    for (int s = 0; s < BSLOTS; ++s) {
+      const uint64_t mk = ballot(slot == s);
+      if (slot == s) rank = mbcnt(mk);
+      if (lane == 0) wc[w][s] = __popcll(mk);
+    }
+    __syncthreads();
+    if (slot >= BSLOT_WAVE) {
+      int before = 0;
+      for (int v = 0; v < w; ++v) before += wc[v][slot];
+      b.list[run[slot] + before + rank] = g;
+    }
+    __syncthreads();
+    if (threadIdx.x < BSLOTS) run[threadIdx.x] += wc[0][threadIdx.x] + wc[1][threadIdx.x] + wc[2][threadIdx.x] +
+                                                   wc[3][threadIdx.x];
+    __syncthreads();
+  }
+}
+
+// Persistent: wavefront gw of G takes chunks gw, gw + G, ... of BATCH_CHUNK list
+// entries of its slot.  A chunk may hold columns of several requests (they are
+// contiguous); each run of one request goes through run_pipe with that request's
+// arguments.  Numeric: requests whose outcome is not OK are skipped.
+template <int E, bool NUM, typename V, bool BM>
+__global__ __launch_bounds__(64 * PIPE_WAVES_PER_BLOCK) void k_batch_wave(BatchArgs b, KArgs a, int slot) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  const int count = b.slotoff[BSLOTS + 1 + slot];
+  const int off = b.slotoff[slot];
+  const int nchunks = (count + BATCH_CHUNK - 1) / BATCH_CHUNK;
+  const int G = (int)gridDim.x * PIPE_WAVES_PER_BLOCK;
+  const int gw = xcd_remap(blockIdx.x, gridDim.x) * PIPE_WAVES_PER_BLOCK + w;
+  unsigned char* base = smem + w * a.slice_bytes;
+  for (int c = gw; c < nchunks; c += G) {
+    const int nu = min(BATCH_CHUNK, count - c * BATCH_CHUNK);
+    const int g = lane < nu ? b.list[off + c * BATCH_CHUNK + lane] : 0;
+    const int rl = lane < nu ? b.req_of[g] : -1;
+    int pos = 0;
+    while (pos < nu) {
+      const int r = readlane(rl, pos);
+      const uint64_t other = ballot(lane > pos && lane < nu && rl != r);
+      const int end = other ? (int)__builtin_ctzll(other) : nu;
+      const BatchReq& q = b.reqs[r];
+      const bool skip = NUM && b.status[r] != 0;
+      if (!skip) {
+        KArgs ta = a;
+        ta.cp = q.cp;
+        ta.ri = q.ri;
+        ta.va = q.va;
+        ta.m = q.m;
+        ta.n = q.n;
+        ta.k = q.k;
+        ta.colcnt = b.colcnt + q.col_base;
+        ta.colptr_c = q.colptr_c;
+        ta.out_r = q.out_r;
+        ta.out_v = q.out_v;
+        if constexpr (BM) pipe_layout(E, NUM, (int)sizeof(V), a.ts_max, q.nq, ta);
+        // this run's columns, local to the request, in lanes 0 .. end - pos - 1
+        const int src = min(lane + pos, nu - 1);
+        const int ucol = __shfl(g, src) - q.col_base;
+        run_pipe<E, NUM, V, BM>(ta, base, end - pos, ucol);
+      }
+      pos = end;
+    }
+  }
+}
+
+// One workgroup per request: colptr(B_r) by an exclusive scan of its column counts.
+__global__ __launch_bounds__(256) void k_batch_scan(BatchArgs b) {
+  __shared__ long long scratch[256 / 64 + 1];
+  const int r = blockIdx.x;
+  if (r >= b.hdr->nreq) return;
+  const BatchReq& q = b.reqs[r];
+  if (b.status[r] & REQ_TOO_LARGE) {  // counts are incomplete: write nothing
+    if (threadIdx.x == 0) b.nnz[r] = -1;
+    return;
+  }
+  const int* cnt = b.colcnt + q.col_base;
+  long long carry = 0;
+  constexpr int PER = 8;
+  for (int tile = 0; tile < q.n; tile += 256 * PER) {
+    const int base = tile + threadIdx.x * PER;
+    int v[PER];
+    long long s = 0;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      v[t] = base + t < q.n ? cnt[base + t] : 0;
+      s += v[t];
+    }
+    long long chunk = 0;
+    long long run = carry + block_excl_scan<256>(s, scratch, &chunk);
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      if (base + t < q.n && run <= INT_MAX) q.colptr_c[base + t] = (int)run;
+      run += v[t];
+    }
+    carry += chunk;
+  }
+  if (threadIdx.x == 0) {
+    if (carry <= INT_MAX) q.colptr_c[q.n] = (int)carry;
+    b.nnz[r] = carry;
+    if (carry > q.cap || carry > INT_MAX) atomicOr(&b.status[r], REQ_CAPACITY);
+  }
+}
+
+// ---- host launchers ----
+void launch_batch_plan(const BatchArgs& b, hipStream_t s) {
+  k_batch_init<<<(b.max_reqs + 255) / 256 > 4 ? (b.max_reqs + 255) / 256 : 4, 256, 0, s>>>(b);
+  k_batch_bounds<<<b.nblk, 256, 0, s>>>(b);
+  k_batch_slot_scan<<<1, 1024, 0, s>>>(b);
+  k_batch_scatter<<<b.nblk, 256, 0, s>>>(b);
+}
+
+void launch_batch_scan(const BatchArgs& b, hipStream_t s) { k_batch_scan<<<b.max_reqs, 256, 0, s>>>(b); }
+
+template <bool NUM, typename V, bool BM>
+static void launch_bw(int wi, const BatchArgs& b, const KArgs& a, unsigned blocks, size_t lds, hipStream_t s) {
+  const int slot = BSLOT_WAVE + 2 * wi + (BM ? 1 : 0);
+  const unsigned nt = 64 * PIPE_WAVES_PER_BLOCK;
+  switch (wi) {
+    case 0: k_batch_wave<1, NUM, V, BM><<<blocks, nt, lds, s>>>(b, a, slot); break;
+    case 1: k_batch_wave<2, NUM, V, BM><<<blocks, nt, lds, s>>>(b, a, slot); break;
+    case 2: k_batch_wave<3, NUM, V, BM><<<blocks, nt, lds, s>>>(b, a, slot); break;
+    case 3: k_batch_wave<4, NUM, V, BM><<<blocks, nt, lds, s>>>(b, a, slot); break;
+    case 4: k_batch_wave<5, NUM, V, BM><<<blocks, nt, lds, s>>>(b, a, slot); break;
+    case 5: k_batch_wave<6, NUM, V, BM><<<blocks, nt, lds, s>>>(b, a, slot); break;
+    case 6: k_batch_wave<8, NUM, V, BM><<<blocks, nt, lds, s>>>(b, a, slot); break;
+    case 7: k_batch_wave<10, NUM, V, BM><<<blocks, nt, lds, s>>>(b, a, slot); break;
+    case 8: k_batch_wave<12, NUM, V, BM><<<blocks, nt, lds, s>>>(b, a, slot); break;
+    default: k_batch_wave<16, NUM, V, BM><<<blocks, nt, lds, s>>>(b, a, slot); break;
+  }
+}
+
+void launch_batch_wave(int wi, bool numeric, bool f64, bool bm, const BatchArgs& b, const KArgs& a, unsigned blocks,
+                       size_t lds, hipStream_t s) {
+  if (!numeric) {
+    if (bm) launch_bw<false, float, true>(wi, b, a, blocks, lds, s);
+    else launch_bw<false, float, false>(wi, b, a, blocks, lds, s);
+  } else if (f64) {
+    if (bm) launch_bw<true, double, true>(wi, b, a, blocks, lds, s);
+    else launch_bw<true, double, false>(wi, b, a, blocks, lds, s);
+  } else {
+    if (bm) launch_bw<true, float, true>(wi, b, a, blocks, lds, s);
+    else launch_bw<true, float, false>(wi, b, a, blocks, lds, s);
+  }
+}
+
+}  // namespace spk

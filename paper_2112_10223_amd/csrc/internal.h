@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "spkadd.h"
+
 namespace spk {
 
 // Column bins.  A column's bin is chosen from its upper bound
@@ -155,5 +157,8 @@ void lds_layout_pipe(int bin, bool numeric, int vbytes, int ts_max, int bm_nq, K
 hipError_t launch_wave_pipe(int bin, bool numeric, bool f64, const KArgs& a, const int* d_list, int nunits,
                             hipStream_t s);
 int max_lds_bytes();
+
+// Sets the calling thread's spkadd_last_error message and returns st (spkadd.cpp).
+spkadd_status report_error(spkadd_status st, const char* msg);
 
 }  // namespace spk

@@ -32,6 +32,18 @@ spkadd_status set_error(spkadd_status st, const char* fmt, ...) {
   return st;
 }
 
+}  // namespace
+
+namespace spk {
+// The thread's last-error message, shared with the batch API (batch.cpp).
+spkadd_status report_error(spkadd_status st, const char* msg) {
+  g_last_error = msg;
+  return st;
+}
+}  // namespace spk
+
+namespace {
+
 #define HIP_TRY(expr)                                                                          \
   do {                                                                                         \
     hipError_t e_ = (expr);                                                                    \

@@ -64,3 +64,21 @@ def test_calls_on_null_plan(L):
     assert L.spkadd_trace_count(None) == 0
     st = binding.Stats()
     assert L.spkadd_get_stats(None, ctypes.byref(st)) == binding.SPKADD_ERR_INVALID
+
+
+def test_batch_argument_checks_without_gpu():
+    """Argument checks of the batch API that return before any device call."""
+    import ctypes
+    from paper_2112_10223_amd import binding
+    L = binding.lib()
+    h = ctypes.c_void_p()
+    assert L.spkadd_batch_create(ctypes.byref(h), binding.SPKADD_F32, 0, 10, 10, None) == binding.SPKADD_ERR_INVALID
+    assert L.spkadd_batch_create(ctypes.byref(h), 7, 4, 10, 10, None) == binding.SPKADD_ERR_INVALID
+    assert L.spkadd_batch_create(None, binding.SPKADD_F32, 4, 10, 10, None) == binding.SPKADD_ERR_INVALID
+    o = binding.make_opts(accum_mode=5)
+    assert L.spkadd_batch_create(ctypes.byref(h), binding.SPKADD_F32, 4, 10, 10, ctypes.byref(o)) == \
+        binding.SPKADD_ERR_INVALID
+    assert L.spkadd_batch_run(None, None, 1, 0, None) == binding.SPKADD_ERR_INVALID
+    assert L.spkadd_batch_results(None, None, None) == binding.SPKADD_ERR_INVALID
+    assert L.spkadd_batch_destroy(None) == binding.SPKADD_OK
+    assert b"NULL" in L.spkadd_last_error() or len(L.spkadd_last_error()) > 0

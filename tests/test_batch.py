@@ -1,0 +1,195 @@
+"""GPU parity of the batched launch (include/spkadd_batch.h) against the CPU oracle.
+
+Each request of a batch is checked on its own: colptr and rowidx bit-exact, values
+bit-exact for integer-valued inputs and within k * u * sum|a| otherwise.  Runs through
+the captured hipGraph are replayed with new requests and host work in between, and
+every replay is checked.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_util import assert_matches, note, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_10223_amd import binding
+    binding.lib()
+
+
+def _random_batches(seed, count, values="int32f"):
+    """Small requests of mixed shapes: short and long columns, tall matrices (hash
+    accumulator) and short ones (bitmap), empty columns, an empty matrix."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for t in range(count):
+        kind = t % 5
+        k = int(rng.integers(1, 13))
+        if kind == 0:
+            m, n, d = int(rng.integers(1, 600)), int(rng.integers(1, 200)), float(rng.uniform(0.5, 8))
+        elif kind == 1:
+            m, n, d = int(rng.integers(9000, 140000)), int(rng.integers(1, 120)), float(rng.uniform(2, 40))
+        elif kind == 2:
+            m, n, d = int(rng.integers(2000, 20000)), int(rng.integers(1, 300)), float(rng.uniform(0, 3))
+        elif kind == 3:
+            m, n, d = int(rng.integers(100, 3000)), int(rng.integers(1, 60)), float(rng.uniform(20, 80))
+        else:
+            m, n, d = int(rng.integers(1, 50)), int(rng.integers(0, 30)), float(rng.uniform(0, 5))
+        d = min(d, m * 0.9)
+        if 2 * k * d > 900:  # keep columns within a wavefront (u <= 1024)
+            d = 900.0 / (2 * k)
+        out.append(workloads.er(m, n, k, d, seed=seed * 1000 + t, values=values))
+    return out
+
+
+def _requests(batches, cap_scale=1.0):
+    import torch
+    reqs, keep = [], []
+    for b in batches:
+        cps, ris, vas = to_device(b)
+        nnz_in = int(sum(int(b.colptr[i, b.n]) for i in range(b.k)))
+        cap = int(nnz_in * cap_scale)
+        colptr_c = torch.full((b.n + 1,), -7, dtype=torch.int32, device="cuda:0")
+        rowidx_c = torch.full((max(cap, 1),), -7, dtype=torch.int32, device="cuda:0")
+        values_c = torch.zeros(max(cap, 1), dtype=vas[0].dtype if vas else torch.float32, device="cuda:0")
+        reqs.append(dict(m=b.m, colptrs=cps, rowidxs=ris, values=vas, colptr_c=colptr_c, rowidx_c=rowidx_c,
+                         values_c=values_c, cap_c=cap))
+        keep.append((cps, ris, vas))
+    return reqs
+
+
+def _check_all(batches, reqs, nnz, status, exact):
+    from paper_2112_10223_amd import binding
+    for b, q, z, st in zip(batches, reqs, nnz, status):
+        assert st == binding.SPKADD_REQ_OK
+        ref = oracle.spkadd(b)
+        assert z == int(ref.colptr[-1])
+        got = (q["colptr_c"].cpu().numpy().astype(np.int64), q["rowidx_c"][:z].cpu().numpy(),
+               q["values_c"][:z].cpu().numpy())
+        assert_matches(b, got, ref, exact_values=exact)
+
+
+def _batch(dtype, nreq, cols, inputs, **kw):
+    from paper_2112_10223_amd import binding
+    return binding.Batch(dtype, nreq, cols, inputs, binding.make_opts(**kw) if kw else None)
+
+
+@pytest.mark.parametrize("values,use_graph", [("int32f", False), ("int32f", True), ("f32", True), ("int64f", True),
+                                              ("f64", False)])
+def test_batch_matches_oracle(values, use_graph):
+    import torch
+    from paper_2112_10223_amd import binding
+    note(f"batch values={values} graph={use_graph}")
+    batches = _random_batches(3, 25, values)
+    reqs = _requests(batches)
+    dtype = binding.SPKADD_F64 if values in ("f64", "int64f") else binding.SPKADD_F32
+    bt = _batch(dtype, 64, 20000, 2000)
+    bt.run(reqs, use_graph=use_graph)
+    nnz, st = bt.results()
+    torch.cuda.synchronize()
+    _check_all(batches, reqs, nnz, st, exact=values.startswith("int"))
+    info = bt.info()
+    assert info["kernels_per_run"] > 5
+    if use_graph:
+        assert info["graphs_captured"] == 1 and info["graph_replays"] == 1
+    bt.close()
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_batch_accumulators(mode):
+    from paper_2112_10223_amd import binding
+    note(f"batch accum_mode={mode}")
+    batches = _random_batches(5, 15, "int32f")
+    reqs = _requests(batches)
+    bt = _batch(binding.SPKADD_F32, 32, 10000, 1000, accum_mode=mode)
+    bt.run(reqs, use_graph=True)
+    nnz, st = bt.results()
+    _check_all(batches, reqs, nnz, st, exact=True)
+    bt.close()
+
+
+def test_batch_graph_replays():
+    """Three runs through one captured graph (same launch shape, new requests each
+    time), with host work between them; every run is checked."""
+    from paper_2112_10223_amd import binding
+    note("batch graph replays")
+    bt = _batch(binding.SPKADD_F32, 64, 20000, 2000)
+    for rep in range(3):
+        batches = _random_batches(11, 25, "int32f") if rep == 0 else _random_batches(11 + rep, 25, "int32f")
+        reqs = _requests(batches)
+        bt.run(reqs, use_graph=True)
+        nnz, st = bt.results()
+        _check_all(batches, reqs, nnz, st, exact=True)  # host work between replays
+    info = bt.info()
+    assert info["graph_replays"] == 3
+    bt.close()
+
+
+def test_batch_too_large_and_capacity():
+    import torch
+    from paper_2112_10223_amd import binding
+    note("batch too large / capacity")
+    small = _random_batches(21, 6, "int32f")
+    big = workloads.er(5000, 10, 4, 400.0, seed=99, values="int32f")  # u about 1600 > 1024
+    batches = small[:3] + [big] + small[3:]
+    reqs = _requests(batches)
+    # request 1 gets too little room for its output
+    ref1 = oracle.spkadd(batches[1])
+    need = int(ref1.colptr[-1])
+    assert need > 2
+    reqs[1]["cap_c"] = need - 1
+    bt = _batch(binding.SPKADD_F32, 16, 5000, 500)
+    bt.run(reqs, use_graph=False)
+    nnz, st = bt.results()
+    torch.cuda.synchronize()
+    assert st[3] == binding.SPKADD_REQ_TOO_LARGE
+    assert st[1] == binding.SPKADD_REQ_CAPACITY and nnz[1] == need
+    assert np.array_equal(reqs[1]["colptr_c"].cpu().numpy().astype(np.int64), ref1.colptr)
+    assert (reqs[1]["rowidx_c"].cpu().numpy() == -7).all()  # nothing written
+    ok = [i for i in range(len(batches)) if i not in (1, 3)]
+    _check_all([batches[i] for i in ok], [reqs[i] for i in ok], [nnz[i] for i in ok], [st[i] for i in ok], True)
+    bt.close()
+
+
+def test_batch_equals_plain_path():
+    """The batched and the one-request launches give identical bits on the same
+    requests (integer-valued inputs: every order of summation is exact)."""
+    from paper_2112_10223_amd import binding
+    note("batch vs plain")
+    batches = _random_batches(31, 12, "int32f")
+    reqs = _requests(batches)
+    bt = _batch(binding.SPKADD_F32, 16, 10000, 500)
+    bt.run(reqs, use_graph=True)
+    nnz, st = bt.results()
+    for b, q, z in zip(batches, reqs, nnz):
+        cps, ris, vas = to_device(b)
+        cp, r, v = binding.spkadd(b.m, cps, ris, vas)
+        assert np.array_equal(cp.cpu().numpy(), q["colptr_c"].cpu().numpy())
+        assert np.array_equal(r.cpu().numpy(), q["rowidx_c"][:z].cpu().numpy())
+        assert np.array_equal(v.cpu().numpy(), q["values_c"][:z].cpu().numpy())
+    bt.close()
+
+
+def test_batch_argument_errors():
+    import torch
+    from paper_2112_10223_amd import binding
+    note("batch argument errors")
+    bt = _batch(binding.SPKADD_F32, 2, 100, 4)
+    b = workloads.er(50, 10, 3, 2.0, seed=1, values="int32f")
+    reqs = _requests([b, b, b])
+    with pytest.raises(binding.SpkaddError):
+        bt.run(reqs)  # three requests, room for two
+    reqs = _requests([workloads.er(50, 80, 3, 2.0, seed=1, values="int32f")] * 2)
+    with pytest.raises(binding.SpkaddError):
+        bt.run(reqs)  # 160 columns, room for 100
+    with pytest.raises(binding.SpkaddError):
+        bt.results()  # no run yet
+    torch.cuda.synchronize()
+    bt.close()
