@@ -108,6 +108,99 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 3) -> None:
     print(json.dumps({"copy_bytes": nbytes, "reps": reps, "source_sha": source_sha()}))
 
 
+def measure_batched(count: int = 120, batch_size: int = 40, max_nnz: int = 1 << 20, reps: int = 3) -> dict:
+    """Small requests of the batched / served workload (a bounded sample: requests
+    whose expected input nnz exceeds max_nnz are redrawn), run (a) one request at a
+    time through plan / symbolic / numeric, (b) batch_size requests per batched run
+    through the captured graph, two batch objects alternating so the host prepares
+    one run while the other executes; requests a batch reports as too large for a
+    wavefront go through the one-request path.  Both timed over the whole sample."""
+    import torch
+    from paper_2112_10223_amd import binding
+    reqs_h = workloads.request_stream(count, max_nnz=max_nnz)
+    dev = torch.device("cuda:0")
+    nnz_in = sum(r.nnz_in for r in reqs_h)
+    reqs = []
+    for r in reqs_h:
+        cps = [torch.from_numpy(np.ascontiguousarray(r.colptr[i])).to(dev) for i in range(r.k)]
+        ris = [torch.from_numpy(x).to(dev) for x in r.rowidx]
+        vas = [torch.from_numpy(x).to(dev) for x in r.vals]
+        cap = max(r.nnz_in, 1)
+        reqs.append(dict(m=r.m, colptrs=binding.PtrArray(cps, True), rowidxs=binding.PtrArray(ris, True),
+                         values=binding.PtrArray(vas, True), colptr_c=torch.empty(r.n + 1, dtype=torch.int32, device=dev),
+                         rowidx_c=torch.empty(cap, dtype=torch.int32, device=dev),
+                         values_c=torch.empty(cap, dtype=torch.float32, device=dev), cap_c=cap, keep=(cps, ris, vas)))
+    stream = binding._stream_ptr(None)
+
+    def plain_one(q):
+        p = binding.spkadd_plan(q["m"], q["colptr_c"].shape[0] - 1, q["colptrs"], q["rowidxs"], binding.SPKADD_F32,
+                                None, stream)
+        binding.spkadd_symbolic(p, q["colptr_c"], stream)
+        binding.spkadd_numeric(p, q["values"], q["rowidx_c"], q["values_c"], stream)
+        p.free()
+
+    def plain_all():
+        for q in reqs:
+            plain_one(q)
+
+    groups = [reqs[i:i + batch_size] for i in range(0, len(reqs), batch_size)]
+    total_cols = max(sum(q["colptr_c"].shape[0] - 1 for q in g) for g in groups)
+    total_inputs = max(sum(len(q["colptrs"]) for q in g) for g in groups)
+    bts = [binding.Batch(binding.SPKADD_F32, batch_size, total_cols, total_inputs) for _ in range(2)]
+    large = []
+
+    def batched_all():
+        large.clear()
+        pending = [None, None]
+        for gi, g in enumerate(groups):
+            bt = bts[gi & 1]
+            if pending[gi & 1] is not None:
+                _, st = bt.results()
+                large.extend(q for q, s in zip(pending[gi & 1], st) if s == binding.SPKADD_REQ_TOO_LARGE)
+            bt.run(g, use_graph=True, stream=stream)
+            pending[gi & 1] = g
+        for slot in (0, 1):
+            if pending[slot] is not None:
+                _, st = bts[slot].results()
+                large.extend(q for q, s in zip(pending[slot], st) if s == binding.SPKADD_REQ_TOO_LARGE)
+        for q in large:
+            plain_one(q)
+
+    times = {}
+    for name, fn in (("plain", plain_all), ("batched", batched_all)):
+        fn()  # warm-up (captures the graphs)
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        times[name] = best
+    # the two paths agree on every request's nnz(B)
+    nnz_b = []
+    for g in groups:
+        bts[0].run(g, use_graph=True, stream=stream)
+        nnz_b += bts[0].results()[0]
+    agree = 0
+    for q, z in zip(reqs, nnz_b):
+        if z >= 0:
+            plain_one(q)
+            torch.cuda.synchronize()
+            agree += int(int(q["colptr_c"][-1].item()) == z)
+    info = bts[0].info()
+    for bt in bts:
+        bt.close()
+    return {"requests": len(reqs), "batch_size": batch_size, "input_nnz": int(nnz_in),
+            "sample": f"{count} requests of the batched workload (k ~ U{{2..64}}, m, n log-U[256, 65536], "
+                      f"density log-U[1e-4, 1e-2] per matrix) with expected input nnz <= {max_nnz}",
+            "plain_ms": round(times["plain"] * 1e3, 3), "batched_ms": round(times["batched"] * 1e3, 3),
+            "plain_nnz_per_s": nnz_in / times["plain"], "batched_nnz_per_s": nnz_in / times["batched"],
+            "speedup": round(times["plain"] / times["batched"], 3), "too_large_routed_plain": len(large),
+            "kernels_per_batched_run": info["kernels_per_run"], "nnz_agree": f"{agree}/{sum(z >= 0 for z in nnz_b)}"}
+
+
 def cpu_baseline(batch, max_cols: int | None = None):
     import oracle
     n = batch.n if max_cols is None else min(batch.n, max_cols)
@@ -131,6 +224,8 @@ def main() -> int:
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-trace", action="store_true", help="time without per-kernel events")
     ap.add_argument("--trace-steps", type=int, default=3, help="untimed steps with every launch traced")
+    ap.add_argument("--batched", type=int, default=120,
+                    help="requests of the batched-vs-plain measurement (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the SpKAdd path here is single-GPU.",
@@ -290,6 +385,8 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    if args.batched > 0:
+        out["batched"] = measure_batched(args.batched)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(batch)
     print(json.dumps(out))

@@ -210,3 +210,32 @@ def config4(values: str = "f32", window: int = 0) -> CSCBatch:
     """k=128 tall-skinny 2^24 x 1024, exactly 4,096 distinct uniform rows per column
     (window > 0: rows drawn from a per-column window of that many rows)."""
     return er(1 << 24, 1024, 128, 4096, seed=SEED + 4, fixed=True, window=window, values=values)
+
+
+def stack(batches) -> CSCBatch:
+    """One batch from several batches of the same shape (their matrices in order)."""
+    m, n = batches[0].m, batches[0].n
+    colptr = np.concatenate([b.colptr for b in batches], axis=0)
+    return CSCBatch(m, n, colptr, [r for b in batches for r in b.rowidx], [v for b in batches for v in b.vals])
+
+
+def request_stream(count: int, *, seed: int = SEED + 5, max_nnz: int | None = None, values: str = "f32"):
+    """Requests of the batched / served workload: k ~ U{2..64}; m and n independent
+    log-uniform in [256, 65536]; each of the k matrices with its own density,
+    log-uniform in [1e-4, 1e-2], and Poisson(density * m) distinct uniform rows per
+    column.  With max_nnz, requests whose expected input nnz exceeds it are redrawn
+    (a bounded sample of the small-request part of the stream)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0
+    while len(out) < count:
+        t += 1
+        k = int(rng.integers(2, 65))
+        m = int(round(np.exp(rng.uniform(np.log(256), np.log(65536)))))
+        n = int(round(np.exp(rng.uniform(np.log(256), np.log(65536)))))
+        dens = np.exp(rng.uniform(np.log(1e-4), np.log(1e-2), size=k))
+        if max_nnz is not None and float(dens.sum()) * m * n > max_nnz:
+            continue
+        mats = [er(m, n, 1, float(d * m), seed=seed * 7919 + t * 131 + i, values=values) for i, d in enumerate(dens)]
+        out.append(stack(mats))
+    return out
