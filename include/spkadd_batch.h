@@ -83,6 +83,10 @@ spkadd_status spkadd_batch_run(spkadd_batch_t b, const spkadd_request* reqs, int
  */
 spkadd_status spkadd_batch_results(spkadd_batch_t b, int64_t* nnz, int32_t* status);
 
+/* 1 when the last run has finished on the device (or there was none), 0 while it
+ * runs.  Does not wait. */
+int32_t spkadd_batch_ready(spkadd_batch_t b);
+
 /* Launches of the last run (kernels enqueued, graph replays). */
 typedef struct spkadd_batch_info {
   int32_t graphs_captured; /* distinct launch shapes captured so far */

@@ -1,0 +1,79 @@
+/*
+ * spkadd_server.h -- a serving loop for SpKAdd requests (continuous batching).
+ *
+ * Clients submit requests (each an SpKAdd, Section II-A) from any thread and wait
+ * on tickets.  A server thread admits requests in arrival order while their output
+ * memory fits the HBM budget and a batch slot is free, groups them into batched runs
+ * (include/spkadd_batch.h) spread over several streams so that runs overlap on the
+ * device, and completes the tickets.  A request that a batch reports as too large
+ * for a wavefront (a column with more than 1024 input entries) goes through the
+ * one-request path (spkadd_plan / spkadd_symbolic / spkadd_numeric) on a stream of its
+ * own.  Requests that arrive while others are on the device join the next run.
+ *
+ * Outputs are allocated by the server (stream-ordered) with the capacity the request
+ * states in cap_c (sum_i nnz(A_i) always suffices) and stay owned by the server until
+ * spkadd_server_release.  Inputs must stay valid until the
+ * ticket completes.
+ */
+#ifndef SPKADD_SERVER_H
+#define SPKADD_SERVER_H
+
+#include "spkadd_batch.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spkadd_server_s* spkadd_server_t;
+
+typedef struct spkadd_server_config {
+  spkadd_dtype dtype;
+  int32_t n_streams;       /* streams that batched runs rotate over (1..8) */
+  int32_t max_batch;       /* requests per batched run (1..4096) */
+  int64_t max_columns;     /* columns per batched run */
+  int64_t max_inputs;      /* inputs (sum of k) per batched run */
+  uint64_t hbm_budget;     /* bytes of output memory the admitted requests may hold */
+  const spkadd_opts* opts; /* NULL for defaults */
+} spkadd_server_config;
+
+#define SPKADD_REQ_ERROR 3 /* the run failed: see spkadd_result.error */
+
+typedef struct spkadd_result {
+  int32_t status;          /* SPKADD_REQ_OK, SPKADD_REQ_CAPACITY or SPKADD_REQ_ERROR */
+  int32_t error;           /* spkadd_status of a failed run, SPKADD_OK otherwise */
+  int32_t path;            /* 0 = batched run, 1 = one-request path */
+  int32_t reserved;
+  int64_t nnz;             /* nnz(B) */
+  int32_t* colptr_c;       /* DEVICE, owned by the server until release */
+  int32_t* rowidx_c;
+  void* values_c;
+  double t_submit, t_start, t_done; /* seconds on the server's steady clock */
+} spkadd_result;
+
+/* Starts the server thread.  Errors: INVALID, OOM, HIP. */
+spkadd_status spkadd_server_create(spkadd_server_t* out, const spkadd_server_config* cfg);
+
+/* Queues a request (a HOST struct; its pointer arrays are copied, its output fields are
+ * ignored).  The request's output memory must fit the budget on its own.
+ * Errors: INVALID (bad request, k > 64, too large for the budget), STATE (stopping). */
+spkadd_status spkadd_server_submit(spkadd_server_t s, const spkadd_request* req, uint64_t* ticket);
+
+/* Waits until the ticket completes (timeout_s < 0: no limit).
+ * Errors: INVALID (unknown ticket), STATE (timeout: the ticket is still pending). */
+spkadd_status spkadd_server_wait(spkadd_server_t s, uint64_t ticket, spkadd_result* out, double timeout_s);
+
+/* Frees the ticket's outputs and forgets it. */
+spkadd_status spkadd_server_release(spkadd_server_t s, uint64_t ticket);
+
+/* Current time on the server's clock (seconds), for stamping arrivals. */
+double spkadd_server_now(spkadd_server_t s);
+
+/* Finishes the runs in flight, cancels the requests not yet admitted (their tickets
+ * complete with status SPKADD_ERR_STATE), stops the threads and frees everything,
+ * including outputs not yet released. */
+spkadd_status spkadd_server_destroy(spkadd_server_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPKADD_SERVER_H */

@@ -308,3 +308,135 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+SPKADD_REQ_ERROR = 3
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("max_columns", ctypes.c_int64), ("max_inputs", ctypes.c_int64), ("hbm_budget", ctypes.c_uint64),
+                ("opts", ctypes.POINTER(Opts))]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("error", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("nnz", ctypes.c_int64), ("colptr_c", ctypes.c_void_p),
+                ("rowidx_c", ctypes.c_void_p), ("values_c", ctypes.c_void_p), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+def _server_fns():
+    L = lib()
+    if not hasattr(L, "_server_bound"):
+        P = ctypes.c_void_p
+        L.spkadd_server_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(ServerConfig)]
+        L.spkadd_server_create.restype = ctypes.c_int
+        L.spkadd_server_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+        L.spkadd_server_submit.restype = ctypes.c_int
+        L.spkadd_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result), ctypes.c_double]
+        L.spkadd_server_wait.restype = ctypes.c_int
+        L.spkadd_server_release.argtypes = [P, ctypes.c_uint64]
+        L.spkadd_server_release.restype = ctypes.c_int
+        L.spkadd_server_now.argtypes = [P]
+        L.spkadd_server_now.restype = ctypes.c_double
+        L.spkadd_server_destroy.argtypes = [P]
+        L.spkadd_server_destroy.restype = ctypes.c_int
+        L.spkadd_batch_ready.argtypes = [P]
+        L.spkadd_batch_ready.restype = ctypes.c_int32
+        L._server_bound = True
+    return L
+
+
+_hip = None
+
+
+def _hip_runtime():
+    """The HIP runtime library (for copies out of server-owned device memory)."""
+    global _hip
+    if _hip is None:
+        import torch  # noqa: F401  (loads the runtime torch was built with)
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    return _hip
+
+
+class Server:
+    """Owning handle of an spkadd_server_t (include/spkadd_server.h)."""
+
+    def __init__(self, dtype=SPKADD_F32, n_streams=2, max_batch=64, max_columns=1 << 20, max_inputs=1 << 14,
+                 hbm_budget=64 << 30, opts: Opts | None = None):
+        L = _server_fns()
+        self._opts = opts
+        cfg = ServerConfig(dtype, n_streams, max_batch, max_columns, max_inputs, hbm_budget,
+                           ctypes.pointer(opts) if opts is not None else None)
+        h = ctypes.c_void_p()
+        _check(L.spkadd_server_create(ctypes.byref(h), ctypes.byref(cfg)))
+        self.handle = h
+        self.dtype = dtype
+        self._keep = {}
+
+    def now(self) -> float:
+        return _server_fns().spkadd_server_now(self.handle)
+
+    def submit(self, m, colptrs, rowidxs, values, cap) -> int:
+        """k device tensors (or PtrArray) each; cap = output capacity in entries."""
+        import torch
+        fb = 0
+        for t in list(colptrs):
+            if isinstance(t, torch.Tensor) and t.data_ptr():
+                fb = t.data_ptr()
+                break
+        cps = colptrs if isinstance(colptrs, PtrArray) else PtrArray(colptrs, True, fb)
+        ris = rowidxs if isinstance(rowidxs, PtrArray) else PtrArray(rowidxs, True, fb)
+        vas = values if isinstance(values, PtrArray) else PtrArray(values, True, fb)
+        n = (colptrs.tensors[0] if isinstance(colptrs, PtrArray) else colptrs[0]).shape[0] - 1
+        req = Request(m, n, len(cps), ctypes.cast(cps.arr, ctypes.c_void_p).value,
+                      ctypes.cast(ris.arr, ctypes.c_void_p).value, ctypes.cast(vas.arr, ctypes.c_void_p).value,
+                      None, None, None, int(cap))
+        tk = ctypes.c_uint64()
+        _check(_server_fns().spkadd_server_submit(self.handle, ctypes.byref(req), ctypes.byref(tk)))
+        self._keep[tk.value] = (cps, ris, vas, n)
+        return tk.value
+
+    def wait(self, ticket: int, timeout: float = -1.0) -> dict:
+        r = Result()
+        _check(_server_fns().spkadd_server_wait(self.handle, ticket, ctypes.byref(r), timeout))
+        out = {name: getattr(r, name) for name, _ in Result._fields_}
+        out["n"] = self._keep[ticket][3]
+        return out
+
+    def outputs(self, res: dict):
+        """Copies of a completed ticket's colptr(B), rows and values (torch, device),
+        made with a device-to-device hipMemcpy of the server-owned arrays."""
+        import torch
+        n, z = res["n"], max(res["nnz"], 0)
+        vdt = torch.float64 if self.dtype == SPKADD_F64 else torch.float32
+        cp = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+        r = torch.empty(max(z, 1), dtype=torch.int32, device="cuda")[:z]
+        v = torch.empty(max(z, 1), dtype=vdt, device="cuda")[:z]
+        hip = _hip_runtime()
+        for dst, src, nbytes in ((cp, res["colptr_c"], 4 * (n + 1)), (r, res["rowidx_c"], 4 * z),
+                                 (v, res["values_c"], v.element_size() * z)):
+            if nbytes:
+                err = hip.hipMemcpy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src), ctypes.c_size_t(nbytes), 3)
+                if err != 0:
+                    raise RuntimeError(f"hipMemcpy failed: {err}")
+        return cp, r, v
+
+    def release(self, ticket: int) -> None:
+        _check(_server_fns().spkadd_server_release(self.handle, ticket))
+        self._keep.pop(ticket, None)
+
+    def close(self):
+        if self.handle:
+            _server_fns().spkadd_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

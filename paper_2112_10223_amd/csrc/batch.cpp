@@ -367,6 +367,16 @@ spkadd_status spkadd_batch_results(spkadd_batch_t b, int64_t* nnz, int32_t* stat
   return SPKADD_OK;
 }
 
+int32_t spkadd_batch_ready(spkadd_batch_t b) {
+  if (!b || b->last_nreq < 0) return 1;
+  const hipError_t e = hipEventQuery(b->ev_done);
+  if (e == hipErrorNotReady) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return 1;  // done, or failed (spkadd_batch_results reports it)
+}
+
 spkadd_status spkadd_batch_get_info(spkadd_batch_t b, spkadd_batch_info* out) {
   if (!b || !out) return fail(SPKADD_ERR_INVALID, "NULL argument");
   out->graphs_captured = (int32_t)b->graphs.size();
