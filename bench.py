@@ -108,7 +108,95 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 3) -> None:
     print(json.dumps({"copy_bytes": nbytes, "reps": reps, "source_sha": source_sha()}))
 
 
-def measure_batched(count: int = 120, batch_size: int = 40, max_nnz: int = 1 << 20, reps: int = 3) -> dict:
+SERVER_CONFIG = {"n_streams": 1, "depth": 1, "max_batch": 32}
+
+
+def measure_served(reqs, plain_service_s: float, plain_one, load: float = 0.8, seed: int = 7,
+                   server_config: dict | None = None) -> dict:
+    """Poisson arrivals at `load` times the rate one-request plain launches can sustain
+    (1 / mean plain service time).  (a) plain: each request at its arrival time, in
+    order, one at a time through plan / symbolic / numeric; (b) served: a submitter
+    thread hands each request to the serving loop at its arrival time.  Latency =
+    completion - arrival; p50 / p99 over all requests."""
+    import threading
+    import torch
+    from paper_2112_10223_amd import binding
+    rng = np.random.default_rng(seed)
+    rate = load / plain_service_s
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
+    nnz_in = sum(int(q["cap_c"]) for q in reqs)
+
+    def wait_until(t0, t):
+        while True:
+            left = t - (time.perf_counter() - t0)
+            if left <= 0:
+                return
+            if left > 2e-4:
+                time.sleep(left - 1e-4)
+
+    # (a) plain, first come first served on one stream
+    lat_plain = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q, a in zip(reqs, arrivals):
+        wait_until(t0, a)
+        plain_one(q)
+        torch.cuda.synchronize()
+        lat_plain.append(time.perf_counter() - t0 - a)
+    span_plain = time.perf_counter() - t0
+    # (b) the serving loop
+    cols = max(int(q["colptr_c"].shape[0]) for q in reqs)
+    sc = dict(SERVER_CONFIG, **(server_config or {}))
+    srv = binding.Server(binding.SPKADD_F32, n_streams=sc["n_streams"], max_batch=sc["max_batch"],
+                         max_columns=max(sc["max_batch"] * cols, 1 << 16), max_inputs=sc["max_batch"] * 64,
+                         hbm_budget=32 << 30, depth=sc["depth"])
+    tickets = [None] * len(reqs)
+    sub_t = [0.0] * len(reqs)
+
+    def submitter(t0s):
+        for i, (q, a) in enumerate(zip(reqs, arrivals)):
+            wait_until(t0s, a)
+            sub_t[i] = srv.now()
+            tickets[i] = srv.submit(q["m"], q["colptrs"], q["rowidxs"], q["values"], q["cap_c"])
+
+    # warm-up: the whole sample once through the server, all at once (captures the
+    # launch shapes of full batches, which cover most of the smaller ones later)
+    warm = [srv.submit(q["m"], q["colptrs"], q["rowidxs"], q["values"], q["cap_c"]) for q in reqs]
+    for tk in warm:
+        srv.wait(tk)
+        srv.release(tk)
+    info0 = srv.info()
+    t0 = time.perf_counter()
+    th = threading.Thread(target=submitter, args=(t0,))
+    th.start()
+    lat_srv, paths, qwait, run = [], [], [], []
+    for i in range(len(reqs)):
+        while tickets[i] is None:
+            time.sleep(0)
+        res = srv.wait(tickets[i])
+        lat_srv.append(res["t_done"] - res["t_submit"])
+        qwait.append(res["t_start"] - res["t_submit"])
+        run.append(res["t_done"] - res["t_start"])
+        paths.append(res["path"])
+        srv.release(tickets[i])
+    th.join()
+    span_srv = time.perf_counter() - t0
+    info = srv.info()
+    srv.close()
+    timed = {key: info[key] - info0[key] for key in ("runs", "batched", "large", "allocations", "graphs_captured",
+                                                     "graph_reuses")}
+    pct = lambda v, p: round(float(np.percentile(np.asarray(v) * 1e3, p)), 3)
+    return {"arrival_rate_per_s": round(rate, 1), "load_vs_plain": load, "requests": len(reqs), "server": sc,
+            "plain": {"p50_ms": pct(lat_plain, 50), "p99_ms": pct(lat_plain, 99),
+                      "nnz_per_s": nnz_in / span_plain},
+            "served": {"p50_ms": pct(lat_srv, 50), "p99_ms": pct(lat_srv, 99), "nnz_per_s": nnz_in / span_srv,
+                       "one_request_path": int(sum(paths)), "p50_admission_wait_ms": pct(qwait, 50),
+                       "p50_run_ms": pct(run, 50), "timed_region": timed},
+            "p99_speedup": round(pct(lat_plain, 99) / max(pct(lat_srv, 99), 1e-9), 3)}
+
+
+def measure_batched(count: int = 120, batch_size: int = 40, max_nnz: int = 1 << 20, reps: int = 3,
+                    serve: bool = True):
     """Small requests of the batched / served workload (a bounded sample: requests
     whose expected input nnz exceeds max_nnz are redrawn), run (a) one request at a
     time through plan / symbolic / numeric, (b) batch_size requests per batched run
@@ -192,7 +280,11 @@ def measure_batched(count: int = 120, batch_size: int = 40, max_nnz: int = 1 << 
     info = bts[0].info()
     for bt in bts:
         bt.close()
-    return {"requests": len(reqs), "batch_size": batch_size, "input_nnz": int(nnz_in),
+    if isinstance(serve, list):  # several server configurations, one measurement each
+        served = [measure_served(reqs, times["plain"] / len(reqs), plain_one, server_config=c) for c in serve]
+    else:
+        served = measure_served(reqs, times["plain"] / len(reqs), plain_one) if serve else None
+    return served, {"requests": len(reqs), "batch_size": batch_size, "input_nnz": int(nnz_in),
             "sample": f"{count} requests of the batched workload (k ~ U{{2..64}}, m, n log-U[256, 65536], "
                       f"density log-U[1e-4, 1e-2] per matrix) with expected input nnz <= {max_nnz}",
             "plain_ms": round(times["plain"] * 1e3, 3), "batched_ms": round(times["batched"] * 1e3, 3),
@@ -386,7 +478,7 @@ def main() -> int:
         "cpu_baseline": None,
     }
     if args.batched > 0:
-        out["batched"] = measure_batched(args.batched)
+        out["served"], out["batched"] = measure_batched(args.batched)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(batch)
     print(json.dumps(out))

@@ -95,7 +95,10 @@ typedef struct spkadd_opts {
   int32_t wave_merge;    /* 0 = merge two adjacent wave bins that each hold >= 1/16 of the
                             wave columns (one kernel then reads neighbouring columns together);
                             1 = keep every wave bin separate */
-  int32_t reserved[1];
+  int32_t batch_fused_cols; /* batched runs (spkadd_batch.h): a run with at most this many
+                              columns in total does each pass in one launch over every wave
+                              bin; larger runs launch one kernel per bin and accumulator.
+                              0 = default (65536), negative = never */
 } spkadd_opts;
 
 typedef struct spkadd_plan_s* spkadd_plan_t;

@@ -58,8 +58,8 @@ typedef struct spkadd_batch_s* spkadd_batch_t;
  * spkadd_batch_create -- a batch for up to max_requests requests per run, with at
  * most max_columns columns and max_inputs inputs (sum of k) over one run.
  *   dtype : value type of every request.
- *   opts  : NULL for defaults; accum_mode and bitmap_ratio apply (force_bin, windows
- *           and load factors do not).
+ *   opts  : NULL for defaults; accum_mode, bitmap_ratio and batch_fused_cols apply
+ *           (force_bin, windows and load factors do not).
  * Errors: INVALID, OOM, HIP.
  */
 spkadd_status spkadd_batch_create(spkadd_batch_t* out, spkadd_dtype dtype, int32_t max_requests,
@@ -87,11 +87,17 @@ spkadd_status spkadd_batch_results(spkadd_batch_t b, int64_t* nnz, int32_t* stat
  * runs.  Does not wait. */
 int32_t spkadd_batch_ready(spkadd_batch_t b);
 
-/* Launches of the last run (kernels enqueued, graph replays). */
+/* Launch statistics.  A run's launch shape is the set of (wave bin, accumulator)
+ * launches its columns can need and its largest bitmap; a run through the graph uses a
+ * graph captured for its own shape or, if there is none, for a shape that covers it
+ * (its extra launches find no columns and exit), and captures its own shape only when
+ * no captured one covers it. */
 typedef struct spkadd_batch_info {
   int32_t graphs_captured; /* distinct launch shapes captured so far */
   int32_t graph_replays;   /* runs launched through a captured graph */
-  int32_t kernels_per_run; /* kernels in one run */
+  int32_t kernels_per_run; /* kernels in the last captured or plainly launched sequence */
+  int32_t graph_reuses;    /* replays of a graph captured for a covering shape */
+  int32_t fused_runs;      /* runs whose passes were one launch each (opts.batch_fused_cols) */
   int32_t reserved;
 } spkadd_batch_info;
 spkadd_status spkadd_batch_get_info(spkadd_batch_t b, spkadd_batch_info* out);

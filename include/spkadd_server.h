@@ -3,17 +3,21 @@
  *
  * Clients submit requests (each an SpKAdd, Section II-A) from any thread and wait
  * on tickets.  A server thread admits requests in arrival order while their output
- * memory fits the HBM budget and a batch slot is free, groups them into batched runs
- * (include/spkadd_batch.h) spread over several streams so that runs overlap on the
- * device, and completes the tickets.  A request that a batch reports as too large
+ * memory fits the HBM budget and a stream has room for another run (config depth),
+ * groups them into batched runs (include/spkadd_batch.h) over one or more streams,
+ * and completes the tickets.  A request that a batch reports as too large
  * for a wavefront (a column with more than 1024 input entries) goes through the
  * one-request path (spkadd_plan / spkadd_symbolic / spkadd_numeric) on a stream of its
  * own.  Requests that arrive while others are on the device join the next run.
  *
- * Outputs are allocated by the server (stream-ordered) with the capacity the request
- * states in cap_c (sum_i nnz(A_i) always suffices) and stay owned by the server until
- * spkadd_server_release.  Inputs must stay valid until the
- * ticket completes.
+ * Outputs are allocated by the server (stream-ordered, or reused from released
+ * tickets) with the capacity the request states in cap_c (sum_i nnz(A_i) always
+ * suffices) and stay owned by the server until spkadd_server_release.  Held and kept
+ * output memory together stay within the HBM budget.  Inputs must stay valid until
+ * the ticket completes.
+ *
+ * While runs are in flight the server thread polls their completion every few
+ * microseconds (one host core busy); idle, it sleeps until a submit.
  */
 #ifndef SPKADD_SERVER_H
 #define SPKADD_SERVER_H
@@ -30,6 +34,11 @@ typedef struct spkadd_server_config {
   spkadd_dtype dtype;
   int32_t n_streams;       /* streams that batched runs rotate over (1..8) */
   int32_t max_batch;       /* requests per batched run (1..4096) */
+  int32_t depth;           /* runs in flight per stream (1 or 2): with 1, requests that
+                              arrive while a stream's run executes wait and join its
+                              next run (larger runs); with 2, the next run is enqueued
+                              behind the running one */
+  int32_t reserved;
   int64_t max_columns;     /* columns per batched run */
   int64_t max_inputs;      /* inputs (sum of k) per batched run */
   uint64_t hbm_budget;     /* bytes of output memory the admitted requests may hold */
@@ -62,11 +71,28 @@ spkadd_status spkadd_server_submit(spkadd_server_t s, const spkadd_request* req,
  * Errors: INVALID (unknown ticket), STATE (timeout: the ticket is still pending). */
 spkadd_status spkadd_server_wait(spkadd_server_t s, uint64_t ticket, spkadd_result* out, double timeout_s);
 
-/* Frees the ticket's outputs and forgets it. */
+/* Gives the ticket's outputs back to the server and forgets the ticket.  The server
+ * keeps released output blocks for later requests of the same size class (a power of
+ * two of at least 64 KiB), so the caller must have finished every use of the outputs,
+ * also work it enqueued on its own streams. */
 spkadd_status spkadd_server_release(spkadd_server_t s, uint64_t ticket);
 
 /* Current time on the server's clock (seconds), for stamping arrivals. */
 double spkadd_server_now(spkadd_server_t s);
+
+typedef struct spkadd_server_info {
+  int64_t runs;            /* batched runs launched */
+  int64_t batched;         /* requests served by batched runs (including those sent on) */
+  int64_t large;           /* requests sent to the one-request path */
+  int64_t allocations;     /* output blocks allocated (the rest were reused) */
+  uint64_t held_bytes;     /* output memory held by tickets */
+  uint64_t pooled_bytes;   /* released output memory kept for reuse */
+  int32_t graphs_captured; /* over every batch object of the server */
+  int32_t graph_reuses;
+} spkadd_server_info;
+
+/* Counters since creation.  Errors: INVALID. */
+spkadd_status spkadd_server_get_info(spkadd_server_t s, spkadd_server_info* out);
 
 /* Finishes the runs in flight, cancels the requests not yet admitted (their tickets
  * complete with status SPKADD_ERR_STATE), stops the threads and frees everything,

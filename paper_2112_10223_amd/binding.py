@@ -34,7 +34,7 @@ class Opts(ctypes.Structure):
                 ("hash_mode", ctypes.c_int32), ("wave_max", ctypes.c_int32), ("load_factor_sym", ctypes.c_float),
                 ("load_factor_num", ctypes.c_float), ("window_fill", ctypes.c_float),
                 ("accum_mode", ctypes.c_int32), ("bitmap_ratio", ctypes.c_float), ("wave_merge", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("batch_fused_cols", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -53,7 +53,8 @@ class Request(ctypes.Structure):
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("graphs_captured", ctypes.c_int32), ("graph_replays", ctypes.c_int32),
-                ("kernels_per_run", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("kernels_per_run", ctypes.c_int32), ("graph_reuses", ctypes.c_int32),
+                ("fused_runs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def declared_functions():
@@ -315,7 +316,7 @@ SPKADD_REQ_ERROR = 3
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int), ("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("max_columns", ctypes.c_int64), ("max_inputs", ctypes.c_int64), ("hbm_budget", ctypes.c_uint64),
+                ("depth", ctypes.c_int32), ("reserved", ctypes.c_int32), ("max_columns", ctypes.c_int64), ("max_inputs", ctypes.c_int64), ("hbm_budget", ctypes.c_uint64),
                 ("opts", ctypes.POINTER(Opts))]
 
 
@@ -324,6 +325,12 @@ class Result(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("nnz", ctypes.c_int64), ("colptr_c", ctypes.c_void_p),
                 ("rowidx_c", ctypes.c_void_p), ("values_c", ctypes.c_void_p), ("t_submit", ctypes.c_double),
                 ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("runs", ctypes.c_int64), ("batched", ctypes.c_int64), ("large", ctypes.c_int64),
+                ("allocations", ctypes.c_int64), ("held_bytes", ctypes.c_uint64), ("pooled_bytes", ctypes.c_uint64),
+                ("graphs_captured", ctypes.c_int32), ("graph_reuses", ctypes.c_int32)]
 
 
 def _server_fns():
@@ -340,6 +347,8 @@ def _server_fns():
         L.spkadd_server_release.restype = ctypes.c_int
         L.spkadd_server_now.argtypes = [P]
         L.spkadd_server_now.restype = ctypes.c_double
+        L.spkadd_server_get_info.argtypes = [P, ctypes.POINTER(ServerInfo)]
+        L.spkadd_server_get_info.restype = ctypes.c_int
         L.spkadd_server_destroy.argtypes = [P]
         L.spkadd_server_destroy.restype = ctypes.c_int
         L.spkadd_batch_ready.argtypes = [P]
@@ -365,11 +374,11 @@ def _hip_runtime():
 class Server:
     """Owning handle of an spkadd_server_t (include/spkadd_server.h)."""
 
-    def __init__(self, dtype=SPKADD_F32, n_streams=2, max_batch=64, max_columns=1 << 20, max_inputs=1 << 14,
-                 hbm_budget=64 << 30, opts: Opts | None = None):
+    def __init__(self, dtype=SPKADD_F32, n_streams=1, max_batch=64, max_columns=1 << 20, max_inputs=1 << 14,
+                 hbm_budget=64 << 30, opts: Opts | None = None, depth=1):
         L = _server_fns()
         self._opts = opts
-        cfg = ServerConfig(dtype, n_streams, max_batch, max_columns, max_inputs, hbm_budget,
+        cfg = ServerConfig(dtype, n_streams, max_batch, depth, 0, max_columns, max_inputs, hbm_budget,
                            ctypes.pointer(opts) if opts is not None else None)
         h = ctypes.c_void_p()
         _check(L.spkadd_server_create(ctypes.byref(h), ctypes.byref(cfg)))
@@ -384,7 +393,7 @@ class Server:
         """k device tensors (or PtrArray) each; cap = output capacity in entries."""
         import torch
         fb = 0
-        for t in list(colptrs):
+        for t in (colptrs.tensors if isinstance(colptrs, PtrArray) else list(colptrs)):
             if isinstance(t, torch.Tensor) and t.data_ptr():
                 fb = t.data_ptr()
                 break
@@ -424,6 +433,11 @@ class Server:
                 if err != 0:
                     raise RuntimeError(f"hipMemcpy failed: {err}")
         return cp, r, v
+
+    def info(self) -> dict:
+        i = ServerInfo()
+        _check(_server_fns().spkadd_server_get_info(self.handle, ctypes.byref(i)))
+        return {name: getattr(i, name) for name, _ in ServerInfo._fields_}
 
     def release(self, ticket: int) -> None:
         _check(_server_fns().spkadd_server_release(self.handle, ticket))

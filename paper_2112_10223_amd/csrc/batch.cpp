@@ -36,15 +36,23 @@ spkadd_status fail(spkadd_status st, const char* fmt, ...) {
   } while (0)
 
 // What a launch sequence depends on besides device data: the largest bitmap of the
-// requests that may use one, and which (wave bin, accumulator) launches can occur.
+// requests that may use one (rounded up to a power of two), and which (wave bin,
+// accumulator) launches can occur.  A sequence captured for a key also serves every
+// key it covers: a launch with no columns of its kind exits at once.
 struct ShapeKey {
+  int fused;  // 1: one launch per pass for every wave slot
   int nq_max;
   unsigned bm_mask, hash_mask;
   bool operator<(const ShapeKey& o) const {
+    if (fused != o.fused) return fused < o.fused;
     if (nq_max != o.nq_max) return nq_max < o.nq_max;
     if (bm_mask != o.bm_mask) return bm_mask < o.bm_mask;
     return hash_mask < o.hash_mask;
   }
+  bool covers(const ShapeKey& o) const {
+    return fused == o.fused && nq_max >= o.nq_max && (o.bm_mask & ~bm_mask) == 0 && (o.hash_mask & ~hash_mask) == 0;
+  }
+  int launches() const { return __builtin_popcount(bm_mask) + __builtin_popcount(hash_mask); }
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -64,6 +72,11 @@ struct spkadd_batch_s {
   // pinned host
   char* h_blob = nullptr;
   size_t blob_bytes = 0;
+  // per-request results: nnz, status and the error flags, one device region and its
+  // pinned mirror with the same layout, copied back in one transfer
+  char* d_res = nullptr;
+  char* h_res = nullptr;
+  size_t res_bytes = 0;
   long long* h_nnz = nullptr;
   int* h_status = nullptr;
   int* h_err = nullptr;
@@ -71,6 +84,9 @@ struct spkadd_batch_s {
   bool upload_pending = false;
   hipStream_t cap_stream = nullptr;
   std::map<ShapeKey, hipGraphExec_t> graphs;
+  int graph_reuses = 0;  // runs served by a graph captured for a covering key
+  long long fused_cols = 65536;  // runs with at most this many columns use the fused launches (< 0: never)
+  int fused_runs = 0;
   BatchArgs args{};
   int last_nreq = -1;
   int graph_replays = 0;
@@ -94,11 +110,49 @@ bool bitmap_for(const spkadd_opts& o, int nq, int E) {
   return (float)nq <= ratio * (float)E;
 }
 
+// The launch arguments of one (wave bin, accumulator) slot of a pass: common fields
+// and the LDS layout of its slice.
+KArgs slot_args(const spkadd_batch_s* b, const ShapeKey& key, int wi, bool bm, bool numeric) {
+  const int vb = b->dtype == SPKADD_F64 ? 8 : 4;
+  const int bin = BIN_W1 + wi;
+  KArgs a{};
+  a.err = b->args.err;
+  a.dummy = b->args.dummy;
+  a.alpha_q = 512;
+  a.hash_mode = 0;
+  a.upw = 1;
+  const int ts = table_slots(64 * wave_bin_E(bin), 512);
+  // the largest bitmap a column of this bin can use: with the automatic choice
+  // only bitmaps of at most bitmap_ratio * E rows of 8192 bits
+  int nq_bin = key.nq_max;
+  if (bm && b->args.accum_mode == SPKADD_ACCUM_AUTO)
+    while (nq_bin > 1 && !((float)nq_bin <= b->args.bitmap_ratio * (float)wave_bin_E(bin))) --nq_bin;
+  lds_layout_pipe(bin, numeric, vb, ts, bm ? nq_bin : 0, a);
+  if (bm) {
+    // each request lays out its own slice for its bitmap size; a smaller bitmap
+    // can need more room (its staged rows and values may not fit over it), so
+    // the launch slice is the largest over every size up to the bin's maximum
+    for (int nq = 1; nq < nq_bin; ++nq) {
+      KArgs t{};
+      lds_layout_pipe(bin, numeric, vb, ts, nq, t);
+      if (t.slice_bytes > a.slice_bytes) a.slice_bytes = t.slice_bytes;
+    }
+  }
+  return a;
+}
+
+unsigned grid_for(const spkadd_batch_s* b, int slice_bytes, int* block_lds) {
+  *block_lds = slice_bytes * PIPE_WAVES_PER_BLOCK;
+  int bpc = max_lds_bytes() / *block_lds;
+  if (bpc > 16 / PIPE_WAVES_PER_BLOCK) bpc = 16 / PIPE_WAVES_PER_BLOCK;
+  if (bpc < 1) bpc = 1;
+  return (unsigned)(b->n_cu * bpc);
+}
+
 // The whole run after the request-table upload.  Returns the kernels enqueued.
 int enqueue_run(spkadd_batch_s* b, const ShapeKey& key, hipStream_t s) {
   int kernels = 0;
   const bool f64 = b->dtype == SPKADD_F64;
-  const int vb = f64 ? 8 : 4;
   launch_batch_plan(b->args, s);
   kernels += 4;
   for (int numeric = 0; numeric < 2; ++numeric) {
@@ -106,34 +160,35 @@ int enqueue_run(spkadd_batch_s* b, const ShapeKey& key, hipStream_t s) {
       launch_batch_scan(b->args, s);
       ++kernels;
     }
+    if (key.fused) {
+      // one launch: the slice is the largest of the slots that can occur
+      KArgs a{};
+      bool any = false;
+      for (int wi = 0; wi < NWAVE_BINS; ++wi)
+        for (int bm = 0; bm < 2; ++bm) {
+          if (!((bm ? key.bm_mask : key.hash_mask) >> wi & 1u)) continue;
+          const KArgs t = slot_args(b, key, wi, bm != 0, numeric != 0);
+          if (!any || t.slice_bytes > a.slice_bytes) a = t;
+          any = true;
+        }
+      if (!any) continue;
+      int block_lds = 0;
+      unsigned blocks = grid_for(b, a.slice_bytes, &block_lds);
+      // persistent: no more blocks than can be resident at once (registers can
+      // limit this kernel more than LDS)
+      const int occ = batch_fused_blocks_per_cu(numeric != 0, f64, (size_t)block_lds);
+      if (occ > 0 && blocks > (unsigned)(b->n_cu * occ)) blocks = (unsigned)(b->n_cu * occ);
+      launch_batch_fused(numeric != 0, f64, b->args, a, blocks, (size_t)block_lds, s);
+      ++kernels;
+      continue;
+    }
     for (int wi = 0; wi < NWAVE_BINS; ++wi) {
       for (int bm = 0; bm < 2; ++bm) {
         if (!((bm ? key.bm_mask : key.hash_mask) >> wi & 1u)) continue;
-        const int bin = BIN_W1 + wi;
-        KArgs a{};
-        a.err = b->args.err;
-        a.dummy = b->args.dummy;
-        a.alpha_q = 512;
-        a.hash_mode = 0;
-        a.upw = 1;
-        const int ts = table_slots(64 * wave_bin_E(bin), 512);
-        lds_layout_pipe(bin, numeric != 0, vb, ts, bm ? key.nq_max : 0, a);
-        if (bm) {
-          // each request lays out its own slice for its bitmap size; a smaller bitmap
-          // can need more room (its staged rows and values may not fit over it), so
-          // the launch slice is the largest over every size up to the batch maximum
-          for (int nq = 1; nq < key.nq_max; ++nq) {
-            KArgs t{};
-            lds_layout_pipe(bin, numeric != 0, vb, ts, nq, t);
-            if (t.slice_bytes > a.slice_bytes) a.slice_bytes = t.slice_bytes;
-          }
-        }
-        const int block_lds = a.slice_bytes * PIPE_WAVES_PER_BLOCK;
-        int bpc = max_lds_bytes() / block_lds;
-        if (bpc > 16 / PIPE_WAVES_PER_BLOCK) bpc = 16 / PIPE_WAVES_PER_BLOCK;
-        if (bpc < 1) bpc = 1;
-        launch_batch_wave(wi, numeric != 0, f64, bm != 0, b->args, a, (unsigned)(b->n_cu * bpc),
-                          (size_t)block_lds, s);
+        const KArgs a = slot_args(b, key, wi, bm != 0, numeric != 0);
+        int block_lds = 0;
+        const unsigned blocks = grid_for(b, a.slice_bytes, &block_lds);
+        launch_batch_wave(wi, numeric != 0, f64, bm != 0, b->args, a, blocks, (size_t)block_lds, s);
         ++kernels;
       }
     }
@@ -177,6 +232,7 @@ spkadd_status spkadd_batch_create(spkadd_batch_t* out, spkadd_dtype dtype, int32
   b->max_reqs = max_requests;
   b->max_cols = max_columns;
   b->max_inputs = max_inputs;
+  b->fused_cols = o.batch_fused_cols == 0 ? 65536 : o.batch_fused_cols < 0 ? -1 : o.batch_fused_cols;
   auto bail = [&](spkadd_status st, const char* what, hipError_t e) {
     (void)hipGetLastError();
     destroy(b);
@@ -206,12 +262,15 @@ spkadd_status spkadd_batch_create(spkadd_batch_t* out, spkadd_dtype dtype, int32
                o_nnz = carve((size_t)max_requests * 8), o_status = carve((size_t)max_requests * 4), o_err = carve(4),
                o_dummy = carve(4096);
   if ((e = hipMalloc((void**)&b->d_ws, off))) return bail(SPKADD_ERR_OOM, "device workspace", e);
-  const size_t h_bytes = b->blob_bytes + (size_t)max_requests * 12 + 64;
+  b->res_bytes = o_err + 4 - o_nnz;
+  const size_t h_bytes = align_up(b->blob_bytes, 256) + b->res_bytes;
   if ((e = hipHostMalloc((void**)&b->h_blob, align_up(h_bytes, 4096), hipHostMallocPortable)))
     return bail(SPKADD_ERR_OOM, "pinned host buffer", e);
-  b->h_nnz = (long long*)(b->h_blob + align_up(b->blob_bytes, 64));
-  b->h_status = (int*)(b->h_nnz + max_requests);
-  b->h_err = b->h_status + max_requests;
+  b->d_res = b->d_ws + o_nnz;
+  b->h_res = b->h_blob + align_up(b->blob_bytes, 256);
+  b->h_nnz = (long long*)b->h_res;
+  b->h_status = (int*)(b->h_res + (o_status - o_nnz));
+  b->h_err = (int*)(b->h_res + (o_err - o_nnz));
   if ((e = hipEventCreateWithFlags(&b->ev_upload, hipEventDisableTiming))) return bail(SPKADD_ERR_HIP, "event", e);
   if ((e = hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming))) return bail(SPKADD_ERR_HIP, "event", e);
   if ((e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking))) return bail(SPKADD_ERR_HIP, "stream", e);
@@ -264,11 +323,13 @@ spkadd_status spkadd_batch_run(spkadd_batch_t b, const spkadd_request* reqs, int
 
   // the previous run's table upload must have left the pinned buffer
   if (b->upload_pending) BHIP(hipEventSynchronize(b->ev_upload));
-  ShapeKey key{0, 0u, 0u};
+  ShapeKey key{0, 0, 0u, 0u};
+  key.fused = b->fused_cols >= 0 && cols <= b->fused_cols ? 1 : 0;
   char* hb = b->h_blob;
   auto* hdr = (BatchHdr*)hb;
   auto* hq = (BatchReq*)(hb + align_up(sizeof(BatchHdr), 64));
-  const size_t ptr_off = align_up(sizeof(BatchHdr), 64) + align_up((size_t)b->max_reqs * sizeof(BatchReq), 64);
+  // the pointer tables follow the descriptors in use, so one copy moves both
+  const size_t ptr_off = align_up(sizeof(BatchHdr), 64) + align_up((size_t)nreq * sizeof(BatchReq), 64);
   auto* hp = (const void**)(hb + ptr_off);
   auto* dp = (const void**)(b->d_blob + ptr_off);
   hdr->nreq = nreq;
@@ -307,22 +368,33 @@ spkadd_status spkadd_batch_run(spkadd_batch_t b, const spkadd_request* reqs, int
     }
     hq[r] = d;
   }
-  // one copy: header, descriptors (only the used ones) and pointer tables
-  BHIP(hipMemcpyAsync(b->d_blob, hb, align_up(sizeof(BatchHdr), 64) + (size_t)nreq * sizeof(BatchReq),
-                      hipMemcpyHostToDevice, stream));
-  BHIP(hipMemcpyAsync(b->d_blob + ptr_off, hb + ptr_off, (size_t)pcur * sizeof(void*), hipMemcpyHostToDevice,
-                      stream));
+  if (key.nq_max > 0) {
+    int p2 = 1;
+    while (p2 < key.nq_max) p2 <<= 1;
+    key.nq_max = p2;
+  }
+  // one copy: header, the descriptors in use and their pointer tables
+  BHIP(hipMemcpyAsync(b->d_blob, hb, ptr_off + (size_t)pcur * sizeof(void*), hipMemcpyHostToDevice, stream));
   BHIP(hipEventRecord(b->ev_upload, stream));
   b->upload_pending = true;
 
   if (use_graph) {
     auto it = b->graphs.find(key);
     if (it == b->graphs.end()) {
+      // the cheapest captured sequence that covers this run
+      for (auto jt = b->graphs.begin(); jt != b->graphs.end(); ++jt)
+        if (jt->first.covers(key) && (it == b->graphs.end() || jt->first.launches() < it->first.launches())) it = jt;
+      if (it != b->graphs.end()) ++b->graph_reuses;
+    }
+    if (it == b->graphs.end()) {
       hipGraph_t g = nullptr;
       hipGraphExec_t x = nullptr;
       BHIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
       const int kernels = enqueue_run(b, key, b->cap_stream);
-      const hipError_t le = hipGetLastError();
+      hipError_t le = hipGetLastError();
+      // the results copy is part of the graph (fixed addresses and size)
+      if (le == hipSuccess)
+        le = hipMemcpyAsync(b->h_res, b->d_res, b->res_bytes, hipMemcpyDeviceToHost, b->cap_stream);
       hipError_t ce = hipStreamEndCapture(b->cap_stream, &g);
       if (le != hipSuccess || ce != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -343,12 +415,11 @@ spkadd_status spkadd_batch_run(spkadd_batch_t b, const spkadd_request* reqs, int
   } else {
     b->kernels_per_run = enqueue_run(b, key, stream);
     BHIP(hipGetLastError());
+    BHIP(hipMemcpyAsync(b->h_res, b->d_res, b->res_bytes, hipMemcpyDeviceToHost, stream));
   }
-  BHIP(hipMemcpyAsync(b->h_nnz, b->args.nnz, (size_t)nreq * 8, hipMemcpyDeviceToHost, stream));
-  BHIP(hipMemcpyAsync(b->h_status, b->args.status, (size_t)nreq * 4, hipMemcpyDeviceToHost, stream));
-  BHIP(hipMemcpyAsync(b->h_err, b->args.err, 4, hipMemcpyDeviceToHost, stream));
   BHIP(hipEventRecord(b->ev_done, stream));
   b->last_nreq = nreq;
+  b->fused_runs += key.fused;
   return SPKADD_OK;
 }
 
@@ -382,7 +453,8 @@ spkadd_status spkadd_batch_get_info(spkadd_batch_t b, spkadd_batch_info* out) {
   out->graphs_captured = (int32_t)b->graphs.size();
   out->graph_replays = b->graph_replays;
   out->kernels_per_run = b->kernels_per_run;
-  out->reserved = 0;
+  out->graph_reuses = b->graph_reuses;
+  out->fused_runs = b->fused_runs;
   return SPKADD_OK;
 }
 

@@ -61,6 +61,13 @@ void launch_batch_plan(const BatchArgs& b, hipStream_t s);
 void launch_batch_scan(const BatchArgs& b, hipStream_t s);
 void launch_batch_wave(int wi, bool numeric, bool f64, bool bm, const BatchArgs& b, const KArgs& a, unsigned blocks,
                        size_t lds, hipStream_t s);
+// Every wave slot of one pass in one launch; `a` holds the common fields and the
+// LDS slice (the largest of the slots).
+void launch_batch_fused(bool numeric, bool f64, const BatchArgs& b, const KArgs& a, unsigned blocks, size_t lds,
+                        hipStream_t s);
+// Blocks of the fused kernel resident per CU with `lds` bytes of LDS per block (0 if
+// the query fails).
+int batch_fused_blocks_per_cu(bool numeric, bool f64, size_t lds);
 // LDS layout of a wave slice (same as the plain launch).
 void lds_layout_pipe(int bin, bool numeric, int vbytes, int ts_max, int bm_nq, KArgs& a);
 

@@ -9,14 +9,14 @@
 //   k_batch_slot_scan / k_batch_scatter  counting sort of the columns by slot;
 //                   inside a slot the columns keep their global order, so each
 //                   request's columns are contiguous
-//   k_batch_wave    persistent wave kernels, one launch per (E, accumulator): chunks
+//   k_batch_wave    persistent wave kernels, one launch per (E, accumulator) (small
+//                   runs use k_batch_fused instead, one launch per pass): chunks
 //                   of the slot's list, split into runs of one request, each run
 //                   through the same per-wavefront pipeline as the plain launch
 //   k_batch_scan    one workgroup per request: colptr(B_r), nnz(B_r), capacity check
 #include <climits>
 
-#include "batch_internal.h"
-#include "wave_device.h"
+#include "batch_device.h"
 
 namespace spk {
 
@@ -97,17 +97,20 @@ __global__ __launch_bounds__(256) void k_batch_bounds(BatchArgs b) {
 }
 
 // One block of 1024 threads; wavefront w scans slots w, w + 16, ... over the bounds
-// blocks.
+// blocks that hold columns of this run (the others find no columns).
 __global__ __launch_bounds__(1024) void k_batch_slot_scan(BatchArgs b) {
   __shared__ int tot[BSLOTS];
   const int lane = lane_id();
+  const int total = b.hdr->total_cols;
+  const int used = total > 0 ? (int)(((long long)total + b.chunk - 1) / b.chunk) : 0;
+  const int nb = used < b.nblk ? used : b.nblk;
   for (int s = threadIdx.x >> 6; s < BSLOTS; s += 16) {
     int carry = 0;
-    for (int base = 0; base < b.nblk; base += 64) {
+    for (int base = 0; base < nb; base += 64) {
       const int t = base + lane;
-      const int v = t < b.nblk ? b.hist[t * BSLOTS + s] : 0;
+      const int v = t < nb ? b.hist[t * BSLOTS + s] : 0;
       const int incl = wave_scan_add(v);
-      if (t < b.nblk) b.hist[t * BSLOTS + s] = carry + incl - v;
+      if (t < nb) b.hist[t * BSLOTS + s] = carry + incl - v;
       carry += readlane(incl, 63);
     }
     if (lane == 0) tot[s] = carry;
@@ -154,52 +157,15 @@ __global__ __launch_bounds__(256) void k_batch_scatter(BatchArgs b) {
   }
 }
 
-// Persistent: wavefront gw of G takes chunks gw, gw + G, ... of BATCH_CHUNK list
-// entries of its slot.  A chunk may hold columns of several requests (they are
-// contiguous); each run of one request goes through run_pipe with that request's
-// arguments.  Numeric: requests whose outcome is not OK are skipped.
+// Persistent, one launch per (wave bin, accumulator): wavefront gw of G takes chunks
+// gw, gw + G, ... of its slot.
 template <int E, bool NUM, typename V, bool BM>
 __global__ __launch_bounds__(64 * PIPE_WAVES_PER_BLOCK) void k_batch_wave(BatchArgs b, KArgs a, int slot) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int lane = lane_id(), w = threadIdx.x >> 6;
-  const int count = b.slotoff[BSLOTS + 1 + slot];
-  const int off = b.slotoff[slot];
-  const int nchunks = (count + BATCH_CHUNK - 1) / BATCH_CHUNK;
+  const int w = threadIdx.x >> 6;
   const int G = (int)gridDim.x * PIPE_WAVES_PER_BLOCK;
   const int gw = xcd_remap(blockIdx.x, gridDim.x) * PIPE_WAVES_PER_BLOCK + w;
-  unsigned char* base = smem + w * a.slice_bytes;
-  for (int c = gw; c < nchunks; c += G) {
-    const int nu = min(BATCH_CHUNK, count - c * BATCH_CHUNK);
-    const int g = lane < nu ? b.list[off + c * BATCH_CHUNK + lane] : 0;
-    const int rl = lane < nu ? b.req_of[g] : -1;
-    int pos = 0;
-    while (pos < nu) {
-      const int r = readlane(rl, pos);
-      const uint64_t other = ballot(lane > pos && lane < nu && rl != r);
-      const int end = other ? (int)__builtin_ctzll(other) : nu;
-      const BatchReq& q = b.reqs[r];
-      const bool skip = NUM && b.status[r] != 0;
-      if (!skip) {
-        KArgs ta = a;
-        ta.cp = q.cp;
-        ta.ri = q.ri;
-        ta.va = q.va;
-        ta.m = q.m;
-        ta.n = q.n;
-        ta.k = q.k;
-        ta.colcnt = b.colcnt + q.col_base;
-        ta.colptr_c = q.colptr_c;
-        ta.out_r = q.out_r;
-        ta.out_v = q.out_v;
-        if constexpr (BM) pipe_layout(E, NUM, (int)sizeof(V), a.ts_max, q.nq, ta);
-        // this run's columns, local to the request, in lanes 0 .. end - pos - 1
-        const int src = min(lane + pos, nu - 1);
-        const int ucol = __shfl(g, src) - q.col_base;
-        run_pipe<E, NUM, V, BM>(ta, base, end - pos, ucol);
-      }
-      pos = end;
-    }
-  }
+  slot_chunks<E, NUM, V, BM, false>(b, a, slot, smem + w * a.slice_bytes, gw, G);
 }
 
 // One workgroup per request: colptr(B_r) by an exclusive scan of its column counts.

@@ -58,6 +58,12 @@ struct Lane {  // one stream and its two batch objects
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+size_t size_class(size_t bytes) {
+  size_t c = 64 * 1024;
+  while (c < bytes) c <<= 1;
+  return c;
+}
+
 }  // namespace
 
 struct spkadd_server_s {
@@ -75,6 +81,11 @@ struct spkadd_server_s {
   bool stop = false;
   std::vector<Lane> lanes;
   hipStream_t large_stream = nullptr, free_stream = nullptr;
+  // released output blocks by size class (power of two, >= 64 KiB), reused by later
+  // requests; held blocks and pooled ones together stay within the budget
+  std::unordered_map<size_t, std::vector<char*>> pool;
+  uint64_t pooled = 0;
+  long long runs = 0, batched = 0, large_count = 0, allocations = 0;
   std::thread loop, large_loop;
 
   double now() const {
@@ -121,9 +132,21 @@ bool retire(spkadd_server_s* s, Lane& ln) {
   return any;
 }
 
+// Frees pooled blocks until `bytes` more fit the budget beside the held and pooled
+// ones (caller holds the lock).  Pooled blocks are idle: their tickets completed.
+void evict(spkadd_server_s* s, size_t bytes) {
+  for (auto it = s->pool.begin(); it != s->pool.end() && s->in_use + s->pooled + bytes > s->cfg.hbm_budget; ++it) {
+    while (!it->second.empty() && s->in_use + s->pooled + bytes > s->cfg.hbm_budget) {
+      (void)hipFreeAsync(it->second.back(), s->free_stream);
+      it->second.pop_back();
+      s->pooled -= it->first;
+    }
+  }
+}
+
 // Forms one batched run on a lane with a free batch object (caller holds the lock).
 bool admit(spkadd_server_s* s, Lane& ln) {
-  if (s->pending.empty() || ln.inflight.size() >= 2) return false;
+  if (s->pending.empty() || (int)ln.inflight.size() >= s->cfg.depth) return false;
   std::vector<uint64_t> ids;
   std::vector<spkadd_request> reqs;
   long long cols = 0, inputs = 0;
@@ -131,10 +154,19 @@ bool admit(spkadd_server_s* s, Lane& ln) {
     Ticket& t = s->tickets[s->pending.front()];
     if (cols + t.n > s->cfg.max_columns || inputs + t.k > s->cfg.max_inputs) break;
     if (s->in_use + t.bytes > s->cfg.hbm_budget) break;
-    if (hipMallocAsync((void**)&t.out, t.bytes, ln.stream) != hipSuccess) {
-      (void)hipGetLastError();
-      t.out = nullptr;
-      break;
+    auto& fl = s->pool[t.bytes];
+    if (!fl.empty()) {
+      t.out = fl.back();
+      fl.pop_back();
+      s->pooled -= t.bytes;
+    } else {
+      evict(s, t.bytes);
+      if (hipMallocAsync((void**)&t.out, t.bytes, ln.stream) != hipSuccess) {
+        (void)hipGetLastError();
+        t.out = nullptr;
+        break;
+      }
+      ++s->allocations;
     }
     s->in_use += t.bytes;
     cols += t.n;
@@ -169,6 +201,8 @@ bool admit(spkadd_server_s* s, Lane& ln) {
     return true;
   }
   ln.inflight.push_back(InFlight{b, ids});
+  ++s->runs;
+  s->batched += (long long)ids.size();
   return true;
 }
 
@@ -189,8 +223,17 @@ void server_loop(spkadd_server_s* s) {
       s->cv_done.notify_all();
       break;
     }
-    const bool busy = running || !s->pending.empty();
-    if (!progress) s->cv_work.wait_for(lk, std::chrono::microseconds(busy ? 50 : 2000));
+    if (progress) continue;
+    if (running) {
+      // runs in flight: poll their completion every few microseconds (a timed wait
+      // on the condition variable wakes up far later than asked)
+      lk.unlock();
+      const auto t1 = std::chrono::steady_clock::now();
+      while (std::chrono::steady_clock::now() - t1 < std::chrono::microseconds(5)) std::this_thread::yield();
+      lk.lock();
+    } else {
+      s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+    }
   }
 }
 
@@ -208,6 +251,7 @@ void large_loop(spkadd_server_s* s) {
     }
     const uint64_t id = s->large.front();
     s->large.pop_front();
+    ++s->large_count;
     Ticket& t = s->tickets[id];
     const int m = t.m, n = t.n, k = t.k;
     const long long cap = t.cap;
@@ -253,6 +297,7 @@ spkadd_status spkadd_server_create(spkadd_server_t* out, const spkadd_server_con
   if (cfg->dtype != SPKADD_F32 && cfg->dtype != SPKADD_F64) return sfail(SPKADD_ERR_INVALID, "bad dtype");
   if (cfg->n_streams < 1 || cfg->n_streams > 8) return sfail(SPKADD_ERR_INVALID, "n_streams must be 1..8");
   if (cfg->max_batch < 1 || cfg->max_batch > 4096) return sfail(SPKADD_ERR_INVALID, "max_batch must be 1..4096");
+  if (cfg->depth < 1 || cfg->depth > 2) return sfail(SPKADD_ERR_INVALID, "depth must be 1 or 2");
   if (cfg->max_columns < 1 || cfg->max_inputs < 1 || cfg->hbm_budget == 0)
     return sfail(SPKADD_ERR_INVALID, "max_columns, max_inputs and hbm_budget must be positive");
   auto* s = new (std::nothrow) spkadd_server_s();
@@ -316,8 +361,8 @@ spkadd_status spkadd_server_submit(spkadd_server_t s, const spkadd_request* req,
     t.ri.push_back(req->rowidx[i]);
     t.va.push_back(req->values[i]);
   }
-  t.bytes = align_up((size_t)(t.n + 1) * 4, 256) + align_up((size_t)t.cap * 4 + 4, 256) +
-            align_up((size_t)t.cap * (size_t)s->vbytes + 8, 256);
+  t.bytes = size_class(align_up((size_t)(t.n + 1) * 4, 256) + align_up((size_t)t.cap * 4 + 4, 256) +
+                       align_up((size_t)t.cap * (size_t)s->vbytes + 8, 256));
   if (t.bytes > s->cfg.hbm_budget) return sfail(SPKADD_ERR_INVALID, "request outputs exceed the budget");
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) return sfail(SPKADD_ERR_STATE, "server is stopping");
@@ -353,11 +398,34 @@ spkadd_status spkadd_server_release(spkadd_server_t s, uint64_t ticket) {
   if (it == s->tickets.end()) return sfail(SPKADD_ERR_INVALID, "unknown ticket");
   if (it->second.state != TState::Done) return sfail(SPKADD_ERR_STATE, "ticket not complete");
   if (it->second.out) {
-    (void)hipFreeAsync(it->second.out, s->free_stream);
+    // kept for reuse: the ticket's work is complete, so the block is idle
+    s->pool[it->second.bytes].push_back(it->second.out);
+    s->pooled += it->second.bytes;
     s->in_use -= it->second.bytes;
   }
   s->tickets.erase(it);
   s->cv_work.notify_all();
+  return SPKADD_OK;
+}
+
+spkadd_status spkadd_server_get_info(spkadd_server_t s, spkadd_server_info* out) {
+  if (!s || !out) return sfail(SPKADD_ERR_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);  // the batch objects are used under this lock only
+  *out = spkadd_server_info{};
+  out->runs = s->runs;
+  out->batched = s->batched;
+  out->large = s->large_count;
+  out->allocations = s->allocations;
+  out->held_bytes = s->in_use;
+  out->pooled_bytes = s->pooled;
+  for (Lane& ln : s->lanes)
+    for (auto& b : ln.batch) {
+      spkadd_batch_info bi{};
+      if (spkadd_batch_get_info(b, &bi) == SPKADD_OK) {
+        out->graphs_captured += bi.graphs_captured;
+        out->graph_reuses += bi.graph_reuses;
+      }
+    }
   return SPKADD_OK;
 }
 
@@ -381,6 +449,8 @@ spkadd_status spkadd_server_destroy(spkadd_server_t s) {
   (void)hipStreamSynchronize(s->large_stream);
   for (auto& kv : s->tickets)
     if (kv.second.out) (void)hipFreeAsync(kv.second.out, s->free_stream);
+  for (auto& kv : s->pool)
+    for (char* p : kv.second) (void)hipFreeAsync(p, s->free_stream);
   (void)hipStreamSynchronize(s->free_stream);
   for (Lane& ln : s->lanes) (void)hipStreamDestroy(ln.stream);
   (void)hipStreamDestroy(s->large_stream);

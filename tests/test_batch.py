@@ -81,34 +81,57 @@ def _batch(dtype, nreq, cols, inputs, **kw):
     return binding.Batch(dtype, nreq, cols, inputs, binding.make_opts(**kw) if kw else None)
 
 
-@pytest.mark.parametrize("values,use_graph", [("int32f", False), ("int32f", True), ("f32", True), ("int64f", True),
-                                              ("f64", False)])
-def test_batch_matches_oracle(values, use_graph):
+# fused_cols: 0 = default (these runs are small enough for the fused launches, one
+# kernel per pass), -1 = one launch per (wave bin, accumulator)
+@pytest.mark.parametrize("values,use_graph,fused_cols", [
+    ("int32f", False, 0), ("int32f", True, 0), ("int32f", False, -1), ("int32f", True, -1), ("f32", True, 0),
+    ("f32", True, -1), ("int64f", True, 0), ("int64f", True, -1), ("f64", False, 0), ("f64", False, -1)])
+def test_batch_matches_oracle(values, use_graph, fused_cols):
     import torch
     from paper_2112_10223_amd import binding
-    note(f"batch values={values} graph={use_graph}")
+    note(f"batch values={values} graph={use_graph} fused_cols={fused_cols}")
     batches = _random_batches(3, 25, values)
     reqs = _requests(batches)
     dtype = binding.SPKADD_F64 if values in ("f64", "int64f") else binding.SPKADD_F32
-    bt = _batch(dtype, 64, 20000, 2000)
+    bt = _batch(dtype, 64, 20000, 2000, batch_fused_cols=fused_cols)
     bt.run(reqs, use_graph=use_graph)
     nnz, st = bt.results()
     torch.cuda.synchronize()
     _check_all(batches, reqs, nnz, st, exact=values.startswith("int"))
     info = bt.info()
-    assert info["kernels_per_run"] > 5
+    assert info["fused_runs"] == (1 if fused_cols == 0 else 0)
+    assert info["kernels_per_run"] == 7 if fused_cols == 0 else info["kernels_per_run"] > 7
     if use_graph:
         assert info["graphs_captured"] == 1 and info["graph_replays"] == 1
     bt.close()
 
 
-@pytest.mark.parametrize("mode", [1, 2])
-def test_batch_accumulators(mode):
+def test_batch_fused_threshold():
+    """Runs with more columns than batch_fused_cols launch per slot, smaller ones fused;
+    both right, the same batch object."""
     from paper_2112_10223_amd import binding
-    note(f"batch accum_mode={mode}")
+    note("batch fused threshold")
+    bt = _batch(binding.SPKADD_F32, 64, 20000, 2000, batch_fused_cols=400)
+    big = _random_batches(13, 20, "int32f")
+    small = [b for b in _random_batches(14, 20, "int32f") if 0 < b.n <= 100][:3]
+    assert sum(b.n for b in big) > 400 and 0 < sum(b.n for b in small) <= 400
+    for batches in (big, small, big):
+        reqs = _requests(batches)
+        bt.run(reqs, use_graph=True)
+        nnz, st = bt.results()
+        _check_all(batches, reqs, nnz, st, exact=True)
+    info = bt.info()
+    assert info["fused_runs"] == 1 and info["graphs_captured"] == 2 and info["graph_replays"] == 3
+    bt.close()
+
+
+@pytest.mark.parametrize("mode,fused_cols", [(1, 0), (2, 0), (1, -1), (2, -1)])
+def test_batch_accumulators(mode, fused_cols):
+    from paper_2112_10223_amd import binding
+    note(f"batch accum_mode={mode} fused_cols={fused_cols}")
     batches = _random_batches(5, 15, "int32f")
     reqs = _requests(batches)
-    bt = _batch(binding.SPKADD_F32, 32, 10000, 1000, accum_mode=mode)
+    bt = _batch(binding.SPKADD_F32, 32, 10000, 1000, accum_mode=mode, batch_fused_cols=fused_cols)
     bt.run(reqs, use_graph=True)
     nnz, st = bt.results()
     _check_all(batches, reqs, nnz, st, exact=True)
@@ -129,6 +152,28 @@ def test_batch_graph_replays():
         _check_all(batches, reqs, nnz, st, exact=True)  # host work between replays
     info = bt.info()
     assert info["graph_replays"] == 3
+    bt.close()
+
+
+def test_batch_covering_graph_reused():
+    """A run whose launch shape is covered by an earlier run's captured graph replays
+    that graph (its extra launches find no columns) instead of capturing a new one,
+    and its results are still right."""
+    from paper_2112_10223_amd import binding
+    note("batch covering graph")
+    bt = _batch(binding.SPKADD_F32, 64, 20000, 2000)
+    batches = _random_batches(41, 30, "int32f")
+    reqs = _requests(batches)
+    bt.run(reqs, use_graph=True)
+    nnz, st = bt.results()
+    _check_all(batches, reqs, nnz, st, exact=True)
+    sub = batches[3:9]
+    reqs = _requests(sub)
+    bt.run(reqs, use_graph=True)
+    nnz, st = bt.results()
+    _check_all(sub, reqs, nnz, st, exact=True)
+    info = bt.info()
+    assert info["graphs_captured"] == 1 and info["graph_reuses"] == 1 and info["graph_replays"] == 2
     bt.close()
 
 

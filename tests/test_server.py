@@ -51,13 +51,14 @@ def _collect(srv, tk):
     return res, (cp.cpu().numpy().astype(np.int64), r.cpu().numpy(), v.cpu().numpy())
 
 
-def test_server_alone_vs_mix():
+@pytest.mark.parametrize("n_streams,depth", [(1, 1), (2, 2)])
+def test_server_alone_vs_mix(n_streams, depth):
     from paper_2112_10223_amd import binding
-    note("server alone vs mix")
+    note(f"server alone vs mix streams={n_streams} depth={depth}")
     targets = _mixed(7, 16)
     targets.append(workloads.er(4000, 12, 3, 500.0, seed=5, values="int32f"))  # too large for a batch
     others = _mixed(8, 40)
-    srv = binding.Server(n_streams=2, max_batch=16, max_columns=4096, max_inputs=256)
+    srv = binding.Server(n_streams=n_streams, max_batch=16, max_columns=4096, max_inputs=256, depth=depth)
     alone = []
     for b in targets:
         tk, keep = _submit(srv, b)
@@ -92,6 +93,11 @@ def test_server_alone_vs_mix():
     for (tk, b) in tickets.values():
         res, got = _collect(srv, tk)
         assert_matches(b, got, oracle.spkadd(b), exact_values=True)
+    info = srv.info()
+    n_req = 2 * len(targets) + len(others)
+    assert info["batched"] == n_req and info["large"] == 2 and info["runs"] >= 1
+    # released output blocks were reused by later requests of the same size class
+    assert info["allocations"] < n_req and info["held_bytes"] == 0 and info["pooled_bytes"] > 0
     srv.close()
 
 
@@ -109,6 +115,8 @@ def test_server_tight_budget_and_real_values():
     for tk, b, _ in pend:
         res, got = _collect(srv, tk)
         assert_matches(b, got, oracle.spkadd(b))
+    info = srv.info()
+    assert info["held_bytes"] == 0 and info["pooled_bytes"] <= 2 << 20
     srv.close()
 
 
