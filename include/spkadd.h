@@ -98,7 +98,7 @@ typedef struct spkadd_opts {
   int32_t batch_fused_cols; /* batched runs (spkadd_batch.h): a run with at most this many
                               columns in total does each pass in one launch over every wave
                               bin; larger runs launch one kernel per bin and accumulator.
-                              0 = default (65536), negative = never */
+                              0 = default (no limit: every run), negative = never */
 } spkadd_opts;
 
 typedef struct spkadd_plan_s* spkadd_plan_t;

@@ -8,8 +8,10 @@
  * and bins of every request's columns (Section III-A), the symbolic pass
  * (Algorithm 6), one exclusive scan per request, and the numeric pass (Algorithm
  * 5) -- all as persistent kernels over one global worklist of columns, so a run
- * costs the same handful of launches however many requests it holds.  The launch
- * sequence is captured once as a hipGraph per launch shape and replayed.
+ * costs the same handful of launches however many requests it holds (seven kernels
+ * and one copy: by default each pass is one launch over every wavefront bin, see
+ * spkadd_opts.batch_fused_cols).  The launch sequence is captured once as a hipGraph
+ * per launch shape and replayed.
  *
  * Outputs go to caller buffers sized by an upper bound: cap_c >= sum_i nnz(A_r,i)
  * always suffices (nnz(B) never exceeds it).  The host learns nnz(B_r) only from

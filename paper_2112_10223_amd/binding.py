@@ -374,7 +374,7 @@ def _hip_runtime():
 class Server:
     """Owning handle of an spkadd_server_t (include/spkadd_server.h)."""
 
-    def __init__(self, dtype=SPKADD_F32, n_streams=1, max_batch=64, max_columns=1 << 20, max_inputs=1 << 14,
+    def __init__(self, dtype=SPKADD_F32, n_streams=1, max_batch=8, max_columns=1 << 20, max_inputs=1 << 14,
                  hbm_budget=64 << 30, opts: Opts | None = None, depth=1):
         L = _server_fns()
         self._opts = opts

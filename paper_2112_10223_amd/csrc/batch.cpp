@@ -85,7 +85,7 @@ struct spkadd_batch_s {
   hipStream_t cap_stream = nullptr;
   std::map<ShapeKey, hipGraphExec_t> graphs;
   int graph_reuses = 0;  // runs served by a graph captured for a covering key
-  long long fused_cols = 65536;  // runs with at most this many columns use the fused launches (< 0: never)
+  long long fused_cols = INT32_MAX;  // runs with at most this many columns use the fused launches (< 0: never)
   int fused_runs = 0;
   BatchArgs args{};
   int last_nreq = -1;
@@ -232,7 +232,7 @@ spkadd_status spkadd_batch_create(spkadd_batch_t* out, spkadd_dtype dtype, int32
   b->max_reqs = max_requests;
   b->max_cols = max_columns;
   b->max_inputs = max_inputs;
-  b->fused_cols = o.batch_fused_cols == 0 ? 65536 : o.batch_fused_cols < 0 ? -1 : o.batch_fused_cols;
+  b->fused_cols = o.batch_fused_cols == 0 ? (long long)INT32_MAX : o.batch_fused_cols < 0 ? -1 : o.batch_fused_cols;
   auto bail = [&](spkadd_status st, const char* what, hipError_t e) {
     (void)hipGetLastError();
     destroy(b);

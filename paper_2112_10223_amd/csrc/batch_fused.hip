@@ -1,6 +1,7 @@
 // The fused batched launch (include/spkadd_batch.h): each pass (symbolic, numeric)
-// of a run in one persistent kernel over every wave slot, for runs with few columns
-// where the per-slot launches would cost more than their work.
+// of a run in one persistent kernel over every wave slot.  Against one launch per
+// slot it saves the launches and the per-slot tails (the waves of a slot kernel wait
+// for its slowest chunk) at the price of the largest slot's registers and LDS.
 #include "batch_device.h"
 
 namespace spk {
@@ -31,8 +32,7 @@ __device__ __forceinline__ void fused_slot(int wi, int bm, const BatchArgs& b, c
 #undef SPK_FUSED_CASE
 }
 
-// Persistent, one launch per pass for every wave slot (runs with few columns, where
-// the launches of the per-slot kernels would cost more than the work).  The chunks of
+// Persistent, one launch per pass for every wave slot.  The chunks of
 // all slots form one sequence, longest columns first; wavefront gw of G takes chunks
 // gw, gw + G, ... of that sequence.  The LDS slice is the largest any slot needs.
 template <bool NUM, typename V>

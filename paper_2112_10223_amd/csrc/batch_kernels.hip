@@ -9,8 +9,8 @@
 //   k_batch_slot_scan / k_batch_scatter  counting sort of the columns by slot;
 //                   inside a slot the columns keep their global order, so each
 //                   request's columns are contiguous
-//   k_batch_wave    persistent wave kernels, one launch per (E, accumulator) (small
-//                   runs use k_batch_fused instead, one launch per pass): chunks
+//   k_batch_wave    persistent wave kernels, one launch per (E, accumulator) (by
+//                   default runs use k_batch_fused instead, one launch per pass): chunks
 //                   of the slot's list, split into runs of one request, each run
 //                   through the same per-wavefront pipeline as the plain launch
 //   k_batch_scan    one workgroup per request: colptr(B_r), nnz(B_r), capacity check
