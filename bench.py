@@ -319,6 +319,7 @@ def main() -> int:
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-trace", action="store_true", help="time without per-kernel events")
     ap.add_argument("--trace-steps", type=int, default=3, help="untimed steps with every launch traced")
+    ap.add_argument("--tune", action="store_true", help="autotune the launch parameters on the workload first")
     ap.add_argument("--batched", type=int, default=400,
                     help="requests of the batched-vs-plain measurement (0 = skip)")
     args = ap.parse_args()
@@ -350,6 +351,17 @@ def main() -> int:
     # kernels); a separate untimed pass traces every launch for the phase breakdown
     opts = binding.make_opts(flags=0 if args.no_trace else binding.SPKADD_FLAG_TRACE_NUMERIC)
     opts_all = binding.make_opts(flags=binding.SPKADD_FLAG_TRACE)
+    tuned = None
+    if args.tune:  # the autotuner on this workload; the timed steps then use its choice
+        best, rep, trials = binding.tune(m, cps, ris, vas, dtype, reps=5)
+        for o in (opts, opts_all):
+            for f in binding.TUNED_FIELDS:
+                setattr(o, f, getattr(best, f))
+        tuned = {"default_ms": round(rep["default_ms"], 4), "best_ms": round(rep["best_ms"], 4),
+                 "trials": rep["trials"], "failed": rep["failed"],
+                 "best": {f: getattr(best, f) for f in binding.TUNED_FIELDS},
+                 "sweep": [{"changed": {f: v for f, v in t["opts"].items() if v != trials[0]["opts"][f]},
+                            "ms": round(t["ms"], 4)} for t in trials]}
 
     # output sizes: one untimed call
     plan = binding.spkadd_plan(m, n, cps, ris, dtype, opts)
@@ -480,6 +492,8 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    if tuned is not None:
+        out["tune"] = tuned
     if args.batched > 0:
         out["served"], out["batched"] = measure_batched(args.batched)
     if not args.no_cpu_baseline:

@@ -454,3 +454,124 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ---- autotuner (include/spkadd_tune.h) ----
+
+class TuneKey(ctypes.Structure):
+    _fields_ = [("arch", ctypes.c_char * 64), ("cus", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("m_log2", ctypes.c_int32), ("n_log2", ctypes.c_int32), ("k_log2", ctypes.c_int32),
+                ("u_log2", ctypes.c_int32)]
+
+
+class TuneTrial(ctypes.Structure):
+    _fields_ = [("opts", Opts), ("ms", ctypes.c_double), ("status", ctypes.c_int32), ("same_colptr", ctypes.c_int32)]
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("trials", ctypes.c_int32), ("failed", ctypes.c_int32), ("default_ms", ctypes.c_double),
+                ("best_ms", ctypes.c_double), ("key", TuneKey)]
+
+
+TUNED_FIELDS = ("wave_max", "accum_mode", "bitmap_ratio", "wave_merge", "load_factor_sym", "load_factor_num",
+                "window_cap", "window_fill")
+
+
+def _tune_fns():
+    L = lib()
+    if not hasattr(L, "_tune_bound"):
+        P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.spkadd_tune_key_for.argtypes = [I32, I32, I32, I64, ctypes.c_int, ctypes.POINTER(TuneKey)]
+        L.spkadd_tune_key_for.restype = ctypes.c_int
+        L.spkadd_tune.argtypes = [I32, I32, I32, P, P, P, ctypes.c_int, ctypes.POINTER(Opts), I32,
+                                  ctypes.POINTER(Opts), ctypes.POINTER(TuneReport), ctypes.POINTER(TuneTrial), I32, P]
+        L.spkadd_tune.restype = ctypes.c_int
+        L.spkadd_tune_lookup.argtypes = [ctypes.POINTER(TuneKey), ctypes.POINTER(Opts), ctypes.POINTER(I32)]
+        L.spkadd_tune_lookup.restype = ctypes.c_int
+        L.spkadd_tune_store.argtypes = [ctypes.POINTER(TuneKey), ctypes.POINTER(Opts), ctypes.c_double]
+        L.spkadd_tune_store.restype = ctypes.c_int
+        L.spkadd_tune_size.argtypes = []
+        L.spkadd_tune_size.restype = I32
+        L.spkadd_tune_save.argtypes = [ctypes.c_char_p]
+        L.spkadd_tune_save.restype = ctypes.c_int
+        L.spkadd_tune_load.argtypes = [ctypes.c_char_p]
+        L.spkadd_tune_load.restype = ctypes.c_int
+        L.spkadd_tune_clear.argtypes = []
+        L.spkadd_tune_clear.restype = None
+        L._tune_bound = True
+    return L
+
+
+def opts_dict(o: Opts) -> dict:
+    return {name: getattr(o, name) for name, _ in Opts._fields_}
+
+
+def tune_key(m, n, k, nnz_in, dtype=SPKADD_F32, arch=None, cus=None) -> TuneKey:
+    """The shape class of an SpKAdd; on the current device unless arch and cus are given
+    (then computed here with the same rule, without a device)."""
+    if arch is None or cus is None:
+        key = TuneKey()
+        _check(_tune_fns().spkadd_tune_key_for(m, n, k, nnz_in, dtype, ctypes.byref(key)))
+        return key
+
+    def clog2(x):
+        return 0 if x <= 1 else int(x - 1).bit_length()
+    u = (nnz_in + n - 1) // n if n > 0 else 0
+    return TuneKey(arch.encode(), cus, dtype, clog2(m), clog2(n), clog2(k), clog2(u) if n > 0 else 0)
+
+
+def tune(m, colptrs, rowidxs, values, dtype=SPKADD_F32, base: Opts | None = None, reps=5, stream=None,
+         max_trials=64):
+    """Runs the tuner on these inputs; returns (best Opts, report dict, [trial dicts])."""
+    n = colptrs[0].shape[0] - 1
+    cp = _ptr_array(colptrs)
+    ri = _ptr_array(rowidxs)
+    va = _ptr_array(values, non_null=True)
+    best = Opts()
+    rep = TuneReport()
+    trials = (TuneTrial * max_trials)()
+    _check(_tune_fns().spkadd_tune(m, n, len(colptrs), ctypes.cast(cp, ctypes.c_void_p),
+                                   ctypes.cast(ri, ctypes.c_void_p), ctypes.cast(va, ctypes.c_void_p), dtype,
+                                   ctypes.byref(base) if base is not None else None, reps, ctypes.byref(best),
+                                   ctypes.byref(rep), trials, max_trials, _stream_ptr(stream)))
+    report = {"trials": rep.trials, "failed": rep.failed, "default_ms": rep.default_ms, "best_ms": rep.best_ms,
+              "key": {name: (getattr(rep.key, name).decode() if name == "arch" else getattr(rep.key, name))
+                      for name, _ in TuneKey._fields_}}
+    out = []
+    for t in trials[:min(rep.trials, max_trials)]:
+        out.append({"opts": {f: getattr(t.opts, f) for f in TUNED_FIELDS}, "ms": t.ms, "status": t.status,
+                    "same_colptr": bool(t.same_colptr)})
+    return best, report, out
+
+
+def tune_lookup(key: TuneKey, opts: Opts | None = None):
+    """Opts with the cached setting of key applied (a copy of opts, or the defaults),
+    or None when the cache has no entry."""
+    o = Opts()
+    if opts is None:
+        lib().spkadd_opts_default(ctypes.byref(o))
+    else:
+        ctypes.pointer(o)[0] = opts
+    found = ctypes.c_int32()
+    _check(_tune_fns().spkadd_tune_lookup(ctypes.byref(key), ctypes.byref(o), ctypes.byref(found)))
+    return o if found.value else None
+
+
+def tune_store(key: TuneKey, opts: Opts, ms: float = -1.0) -> None:
+    _check(_tune_fns().spkadd_tune_store(ctypes.byref(key), ctypes.byref(opts), ms))
+
+
+def tune_size() -> int:
+    return _tune_fns().spkadd_tune_size()
+
+
+def tune_save(path: str) -> None:
+    _check(_tune_fns().spkadd_tune_save(os.fsencode(path)))
+
+
+def tune_load(path: str) -> None:
+    _check(_tune_fns().spkadd_tune_load(os.fsencode(path)))
+
+
+def tune_clear() -> None:
+    _tune_fns().spkadd_tune_clear()
