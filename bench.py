@@ -77,7 +77,7 @@ def kernel_of_column(u: np.ndarray, cap: int, wave_max: int = 1024, merge: bool 
 
 def source_sha() -> str:
     h = hashlib.sha256()
-    for fn in ("hash_kernels.hip", "wave_kernels.hip", "hash_common.h", "device.h", "internal.h"):
+    for fn in ("hash_kernels.hip", "wave_kernels.hip", "wave_device.h", "hash_common.h", "device.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_2112_10223_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
