@@ -144,6 +144,14 @@ __device__ __forceinline__ T block_sum(T x, T* scratch) {
 // Blocks are handed to the 8 XCDs of the device round-robin (block b runs on XCD
 // b % 8).  This remaps the hardware block id so that each XCD gets a contiguous run
 // of logical blocks, which keeps neighbouring columns in one XCD's L2.
+// A wave-uniform 64-bit value moved into scalar registers (lane 0's copy).  The
+// builtin returns int: each half goes through unsigned so it is not sign-extended.
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long x) {
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(x >> 32));
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)x);
+  return ((unsigned long long)hi << 32) | (unsigned long long)lo;
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int G) {
   const int x = b & 7, q = b >> 3;
   const int per = G >> 3, rem = G & 7;

@@ -30,8 +30,8 @@ namespace spk {
 // plus mbcnt over the chunk's mask word.  Lanes past the end take the unit's last
 // entry (every unit has u > 0), so no load is masked off.
 template <int E, bool NUM, typename V>
-__device__ __forceinline__ void issue_unit_loads(const KArgs& a, unsigned char* base, const long long* adj,
-                                                 const long long* adjv, int u, int (&rows)[E], V (&vals)[E]) {
+__device__ __forceinline__ void issue_unit_loads(const KArgs& a, unsigned char* base, const long long* adj, int u,
+                                                 int (&rows)[E], V (&vals)[E]) {
   const int lane = lane_id();
   const unsigned long long* sb = reinterpret_cast<const unsigned long long*>(base + a.off_mark);
   long long ar[E], av[E];
@@ -45,8 +45,13 @@ __device__ __forceinline__ void issue_unit_loads(const KArgs& a, unsigned char* 
     const unsigned long long S = ((unsigned long long)hi << 32) | (unsigned long long)lo;
     const int seg = before + (int)(S & 1ull) + mbcnt(S >> 1);
     before += __popcll(S);
-    ar[t] = adj[seg];
-    if (NUM) av[t] = adjv[seg];
+    if constexpr (NUM) {  // (rows, values) pointer pairs: one 16-byte read
+      const longlong2 pr = reinterpret_cast<const longlong2*>(adj)[seg];
+      ar[t] = pr.x;
+      av[t] = pr.y;
+    } else {
+      ar[t] = adj[seg];
+    }
   }
 #pragma unroll
   for (int t = 0; t < E; ++t) {
@@ -72,15 +77,19 @@ __device__ __forceinline__ void issue_meta_loads(const KArgs& a, long long cpp, 
 // them, in segment order, and the start mask.  Returns u.
 template <int E, bool NUM, typename V>
 __device__ __forceinline__ int build_unit_meta(const KArgs& a, unsigned char* base, long long rip, long long vap,
-                                               int s, int e, long long* adj, long long* adjv) {
+                                               int s, int e, long long* adj) {
   const int lane = lane_id();
   const int len = lane < a.k ? e - s : 0;
   const int incl = wave_scan_add(len);
   const int ex = incl - len;
   const int ord = mbcnt(ballot(len > 0));
   if (len > 0) {
-    adj[ord] = rip + 4LL * (s - ex);
-    if (NUM) adjv[ord] = vap + (long long)sizeof(V) * (s - ex);
+    // numeric: (rows, values) pointer pairs in the 16-byte slots of adj (its region
+    // holds 64 pairs there)
+    if constexpr (NUM)
+      reinterpret_cast<longlong2*>(adj)[ord] = make_longlong2(rip + 4LL * (s - ex), vap + (long long)sizeof(V) * (s - ex));
+    else
+      adj[ord] = rip + 4LL * (s - ex);
   }
   unsigned* sb = reinterpret_cast<unsigned*>(base + a.off_mark);
   if (lane < 2 * E) sb[lane] = 0u;
@@ -127,11 +136,24 @@ __device__ __forceinline__ void write_column(const KArgs& a, int o0, int c, cons
   int* ob = live ? a.out_r + o0 : reinterpret_cast<int*>((char*)a.dummy + 2048);
   V* ov = live ? (V*)a.out_v + o0 : reinterpret_cast<V*>((char*)a.dummy + 2048 + 64);
   const int last = live ? c - 1 : 0;
+  // every staged entry is read before the first store (one LDS round trip)
+  int rr[E];
+  V vv[E];
 #pragma unroll
   for (int t = 0; t < E; ++t) {
     const int q = min(64 * t + lane, last);
-    gstore<int>((long long)(ob + q), br[q]);
-    gstore<V>((long long)(ov + q), bv[q]);
+    rr[t] = br[q];
+    vv[t] = bv[q];
+  }
+  // uniform base (in scalar registers) + zero-extended 32-bit offset: no 64-bit
+  // address arithmetic per lane
+  const unsigned long long sob = uniform_u64((unsigned long long)ob);
+  const unsigned long long sov = uniform_u64((unsigned long long)ov);
+#pragma unroll
+  for (int t = 0; t < E; ++t) {
+    const unsigned q = (unsigned)min(64 * t + lane, last);
+    gstore<int>((long long)(sob + (unsigned long long)(q * 4u)), rr[t]);
+    gstore<V>((long long)(sov + (unsigned long long)(q * (unsigned)sizeof(V))), vv[t]);
   }
 }
 
@@ -326,7 +348,9 @@ __device__ __forceinline__ void bm_num_unit(const KArgs& a, unsigned char* base,
   unsigned* bm = reinterpret_cast<unsigned*>(bm4);
   unsigned short* pw = reinterpret_cast<unsigned short*>(base + a.off_pre);  // set bits below each word pair
   V* bv = reinterpret_cast<V*>(base + a.off_bvals);  // may overlay the bitmap (used after the ranks)
-  int* br = reinterpret_cast<int*>(base + a.off_brows);
+  // rows follow the 64 (E + 1) staged values (a.off_brows; a constant distance, so
+  // one address serves both)
+  int* br = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(bv) + 64 * (E + 1) * sizeof(V));
   const int nq = a.bm_nq;
   for (int q = 0; q < nq; ++q) bm4[q * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
   wave_sync();
@@ -341,16 +365,27 @@ __device__ __forceinline__ void bm_num_unit(const KArgs& a, unsigned char* base,
   }
   wave_sync();
   // exclusive popcount prefix per pair of words (ranks stay below 64 E <= 1024, so
-  // 16 bits hold them); lane handles the 4 words (2 pairs) of group q*64 + lane
+  // 16 bits hold them); lane handles the 4 words (2 pairs) of group q*64 + lane.
+  // Two bitmap rows share one scan, one in each 16-bit half: no partial sum exceeds
+  // the column's distinct rows (<= 1024), so the halves never carry into each other.
   int carry = 0;
-  for (int q = 0; q < nq; ++q) {
+  for (int q = 0; q < nq; q += 2) {
+    const bool two = q + 1 < nq;
     const uint4 x = bm4[q * 64 + lane];
-    const int c01 = __popc(x.x) + __popc(x.y), c23 = __popc(x.z) + __popc(x.w);
-    const int n = c01 + c23;
-    const int incl = wave_scan_add(n);
-    const int p0 = carry + incl - n;
-    carry += readlane(incl, 63);
-    reinterpret_cast<unsigned*>(pw)[q * 64 + lane] = (unsigned)p0 | ((unsigned)(p0 + c01) << 16);
+    const uint4 y = two ? bm4[(q + 1) * 64 + lane] : make_uint4(0u, 0u, 0u, 0u);
+    const int x01 = __popc(x.x) + __popc(x.y), nx = x01 + __popc(x.z) + __popc(x.w);
+    const int y01 = __popc(y.x) + __popc(y.y), ny = y01 + __popc(y.z) + __popc(y.w);
+    const int packed = nx | (ny << 16);
+    const int incl = wave_scan_add(packed);
+    const int ex = incl - packed;
+    const int tot = readlane(incl, 63);
+    const int px = carry + (ex & 0xffff);
+    carry += tot & 0xffff;
+    const int py = carry + (ex >> 16);
+    carry += tot >> 16;
+    unsigned* pw32 = reinterpret_cast<unsigned*>(pw);
+    pw32[q * 64 + lane] = (unsigned)px | ((unsigned)(px + x01) << 16);
+    if (two) pw32[(q + 1) * 64 + lane] = (unsigned)py | ((unsigned)(py + y01) << 16);
   }
   int c = carry;
   if (c != cnt) {
@@ -361,14 +396,25 @@ __device__ __forceinline__ void bm_num_unit(const KArgs& a, unsigned char* base,
   wave_sync();
   // rank(row) = set bits below it = output position; the first entry of a row puts
   // the row and its value there, later entries of the row add their values
+  // every lookup is issued before the first is used (one LDS round trip, not E)
+  // (the word is picked by masking, not by a select: a select between two array
+  // elements is turned into an indexed scratch access)
   int rk[E];
+  unsigned plo[E], phi[E], pp[E];
+#pragma unroll
+  for (int t = 0; t < E; ++t) {
+    const int w = (lane + 64 * t < u ? rows[t] : 0) >> 5;
+    const uint2 pr = reinterpret_cast<const uint2*>(bm)[w >> 1];
+    plo[t] = pr.x;
+    phi[t] = pr.y;
+    pp[t] = pw[w >> 1];
+  }
 #pragma unroll
   for (int t = 0; t < E; ++t) {
     const int r = lane + 64 * t < u ? rows[t] : 0;
-    const int w = r >> 5;
-    const uint2 pr = reinterpret_cast<const uint2*>(bm)[w >> 1];
-    const unsigned word = (w & 1) ? pr.y : pr.x;
-    rk[t] = (int)pw[w >> 1] + ((w & 1) ? __popc(pr.x) : 0) + __popc(word & ((1u << (r & 31)) - 1u));
+    const unsigned odd = 0u - (unsigned)((r >> 5) & 1);  // all ones for the second word of the pair
+    const unsigned word = plo[t] ^ ((plo[t] ^ phi[t]) & odd);
+    rk[t] = (int)pp[t] + (int)((unsigned)__popc(plo[t]) & odd) + __popc(word & ((1u << (r & 31)) - 1u));
   }
   wave_sync();  // the bitmap is read for the last time above
   // entries that are not first write into per-lane sink slots 64 E + lane
@@ -443,16 +489,15 @@ __device__ __forceinline__ void pipe_step(const KArgs& a, unsigned char* base, i
     // one segment table: a unit's pointers are read into registers in the step
     // that writes them
     long long* adj = (long long*)(base + a.off_adj);
-    long long* adjv = (long long*)(base + a.off_adjv);
     nxt.j = t + 1 < nu ? readlane(ucol, t + 1) : -1;  // -1: a replay, no output
-    nxt.u = build_unit_meta<E, NUM, V>(a, base, rip, vap, ms, me, adj, adjv);
+    nxt.u = build_unit_meta<E, NUM, V>(a, base, rip, vap, ms, me, adj);
     if (NUM) {
       nxt.o0 = readlane(mc, 0);
       nxt.cnt = readlane(mc, 1) - nxt.o0;
     }
     issue_meta_loads<NUM>(a, cpp, readlane(ucol, min(t + 2, nu - 1)), ms, me, mc);
     wave_sync();
-    issue_unit_loads<E, NUM, V>(a, base, adj, adjv, nxt.u, nxt.rows, nxt.vals);
+    issue_unit_loads<E, NUM, V>(a, base, adj, nxt.u, nxt.rows, nxt.vals);
   }
   if constexpr (NUM && BM) {
     bm_num_unit<E, V>(a, base, cur.u, cur.cnt, cur.o0, cur.j >= 0, cur.rows, cur.vals);
@@ -495,8 +540,7 @@ __device__ __forceinline__ void run_pipe(const KArgs& a, unsigned char* base, in
   issue_meta_loads<NUM>(a, cpp, readlane(ucol, 0), ms, me, mc);
   {
     long long* adj = (long long*)(base + a.off_adj);
-    long long* adjv = (long long*)(base + a.off_adjv);
-    A.u = build_unit_meta<E, NUM, V>(a, base, rip, vap, ms, me, adj, adjv);
+    A.u = build_unit_meta<E, NUM, V>(a, base, rip, vap, ms, me, adj);
     A.j = readlane(ucol, 0);
     if (NUM) {
       A.o0 = readlane(mc, 0);
@@ -504,7 +548,7 @@ __device__ __forceinline__ void run_pipe(const KArgs& a, unsigned char* base, in
     }
     issue_meta_loads<NUM>(a, cpp, readlane(ucol, min(1, nu - 1)), ms, me, mc);
     wave_sync();
-    issue_unit_loads<E, NUM, V>(a, base, adj, adjv, A.u, A.rows, A.vals);
+    issue_unit_loads<E, NUM, V>(a, base, adj, A.u, A.rows, A.vals);
   }
   if constexpr (!NUM && BM) {  // the symbolic bitmap starts all zero and stays so
     uint4* bm4 = reinterpret_cast<uint4*>(base + a.off_bm);
@@ -523,7 +567,7 @@ __device__ __forceinline__ void run_pipe(const KArgs& a, unsigned char* base, in
 // sink slots, then values and the 256-bucket histogram) or the bitmap (nq x 1 KiB)
 // with its pair prefix (nq x 256 B); for the numeric bitmap the rows and values
 // staged by rank overlay the bitmap when they fit in it.  Then the start mask
-// (E 64-bit words) and the segment pointer tables.
+// (E 64-bit words) and the segment pointer table.
 __host__ __device__ inline void pipe_layout(int E, bool numeric, int vbytes, int ts_max, int bm_nq, KArgs& a) {
   int hash_bytes = (ts_max + 64) * 4;
   if (numeric) hash_bytes += (ts_max + 64) * vbytes + 272 * 4;
@@ -544,10 +588,9 @@ __host__ __device__ inline void pipe_layout(int E, bool numeric, int vbytes, int
   off += 8 * E;
   off = (off + 15) & ~15;
   a.off_P = off;
-  a.off_adj = off;
-  off += 64 * 8;
-  a.off_adjv = off;
-  if (numeric) off += 64 * 8;
+  a.off_adj = off;  // numeric: 64 (rows, values) pointer pairs; symbolic: 64 row pointers
+  off += numeric ? 64 * 16 : 64 * 8;
+  a.off_adjv = a.off_adj;  // (inside the pairs)
   a.slice_bytes = (off + 15) & ~15;
   a.ts_max = ts_max;
 }
