@@ -144,6 +144,18 @@ __device__ __forceinline__ T block_sum(T x, T* scratch) {
 // Blocks are handed to the 8 XCDs of the device round-robin (block b runs on XCD
 // b % 8).  This remaps the hardware block id so that each XCD gets a contiguous run
 // of logical blocks, which keeps neighbouring columns in one XCD's L2.
+// Loads and stores through a 64-bit address known to be global memory (not a
+// generic pointer: generic accesses share the LDS wait counter).
+template <typename T>
+__device__ __forceinline__ T gload(long long addr) {
+  return *(const __attribute__((address_space(1))) T*)addr;
+}
+
+template <typename T>
+__device__ __forceinline__ void gstore(long long addr, T v) {
+  *(__attribute__((address_space(1))) T*)addr = v;
+}
+
 // A wave-uniform 64-bit value moved into scalar registers (lane 0's copy).  The
 // builtin returns int: each half goes through unsigned so it is not sign-extended.
 __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long x) {

@@ -28,16 +28,6 @@ __device__ __forceinline__ int hash_slot(int r, int TS, int mode) {
   return (int)(((uint64_t)h * (uint32_t)TS) >> 32);
 }
 
-template <typename T>
-__device__ __forceinline__ T gload(long long addr) {
-  return *(const __attribute__((address_space(1))) T*)addr;
-}
-
-template <typename T>
-__device__ __forceinline__ void gstore(long long addr, T v) {
-  *(__attribute__((address_space(1))) T*)addr = v;
-}
-
 // Algorithm 6 (HashSymbolic) on one row: 1 if r was not stored yet.
 __device__ __forceinline__ int sym_insert(int* T, int TS, int r, int mode, int* err) {
   int s = hash_slot(r, TS, mode);

@@ -39,9 +39,23 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_bounds(PlanParams p, const int
   long long uj = 0;
   int b = -1;
   if (j < p.n) {
-    for (int i = 0; i < p.k; ++i) {
-      const int* c = cp[i];
-      uj += (long long)(c[j + 1] - c[j]);
+    // 16 inputs per round, all their loads in flight before the first is used (the
+    // loop is bound by memory latency, not bandwidth: one column per thread)
+    for (int i0 = 0; i0 < p.k; i0 += 16) {
+      long long ptr[16];
+      int s[16], e[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) ptr[t] = (long long)cp[min(i0 + t, p.k - 1)];
+      // (global loads: through a generic pointer they would share the scalar loads'
+      // wait counter and be waited for one by one)
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        s[t] = gload<int>(ptr[t] + 4LL * j);
+        e[t] = gload<int>(ptr[t] + 4LL * (j + 1));
+      }
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+        if (i0 + t < p.k) uj += (long long)(e[t] - s[t]);
     }
     if (uj > INT_MAX) {
       atomicOr(&sum->err, ERR_OVERFLOW);
