@@ -69,7 +69,7 @@ __device__ __forceinline__ int build_meta(const KArgs& a, int j, bool win, int b
     if (i < a.k) {
       if (win) {
         s = a.bpos[(long long)blo * a.k + i];
-        e = a.bpos[(long long)(blo + 1) * a.k + i];
+        e = max(a.bpos[(long long)(blo + 1) * a.k + i], s);  // (only an unsorted input could invert them)
       } else {
         const int* c = a.cp[i];
         s = c[j];

@@ -211,6 +211,7 @@ __global__ __launch_bounds__(NT) void k_hash_wg(KArgs a, const int* __restrict__
   } else {
     j = list[unit];
   }
+  if (rhi - rlo <= a.wg_span_max) return;  // the bitmap kernel's unit (uniform; wg_span_max = 0: none)
   int* K = (int*)smem;
   V* Vt = (V*)(smem + a.ts_max * 4);
   int* P = (int*)(smem + a.off_P);

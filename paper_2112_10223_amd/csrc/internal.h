@@ -60,7 +60,9 @@ struct PlanSummary {
   int err;
   int bin_count[NBINS];
   int n_windows;
-  int pad;
+  int pad;       // windows still to refine (one refinement level)
+  int max_span;  // widest window (rows) of the last level counted
+  int pad2;
 };
 
 // Arguments of the per-unit symbolic / numeric kernels.
@@ -92,6 +94,9 @@ struct KArgs {
   int off_P, off_adj, off_adjv, off_hist, off_match, off_mark, slice_bytes;
   int bm_nq;              // wave bitmap mode: bitmap rows of 256 words (0 = hash mode)
   int off_bm, off_pre, off_bvals, off_brows;
+  // workgroup units: units at most wg_span_max rows wide go to the bitmap kernel (the
+  // hash kernel skips them); wg_cap = its staging capacity in output entries
+  int wg_span_max, wg_cap;
 };
 
 // ---- plan kernels (plan_kernels.hip) ----
@@ -117,8 +122,8 @@ void launch_win_scan(const PlanParams& p, const int* d_list, const int* d_binoff
 void launch_win_fill(const PlanParams& p, int n_wcols, const int* d_wfirst, int* d_win_c, int* d_brow, int* d_bcol,
                      hipStream_t s);
 void launch_win_search(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
-                       const int* d_wfirst, int n_bounds, const int* d_bcol, const int* d_brow, int* d_bpos,
-                       hipStream_t s);
+                       const int* d_wfirst, const int* d_u, int n_wcols, int n_bounds, const int* d_bcol,
+                       const int* d_brow, int* d_bpos, hipStream_t s);
 void launch_win_count(const PlanParams& p, int n_windows, const int* d_win_c, const int* d_brow, const int* d_bpos,
                       int* d_cntin, int* d_q, PlanSummary* d_sum, hipStream_t s);
 void launch_win_refine_fill(int n_windows, int n_wcols, const int* d_win_c, const int* d_wfirst_old,
@@ -154,6 +159,12 @@ const char* hash_kernel_name(int bin, bool numeric);
 // Pipelined wave-bin kernels (wave_kernels.hip): k <= 64 and numeric load factor 1/2.
 bool wave_pipe_ok(int k, int alpha_num_q);
 void lds_layout_pipe(int bin, bool numeric, int vbytes, int ts_max, int bm_nq, KArgs& a);
+// Workgroup bitmap kernel (bitmap_wg.hip): widest unit it takes (rows), LDS layout,
+// launch over a bin's units (G1, G2 or WIN).
+int bitmap_wg_span_max();
+void lds_layout_bitmap_wg(bool numeric, int vbytes, int k, int span_max, int cap, KArgs& a);
+hipError_t launch_bitmap_wg(int bin, bool numeric, bool f64, const KArgs& a, const int* d_list, int nunits,
+                            hipStream_t s);
 hipError_t launch_wave_pipe(int bin, bool numeric, bool f64, const KArgs& a, const int* d_list, int nunits,
                             hipStream_t s);
 int max_lds_bytes();

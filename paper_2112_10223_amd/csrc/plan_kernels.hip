@@ -275,17 +275,31 @@ __device__ __forceinline__ int lower_bound_rows(const int* __restrict__ r, int l
   return lo;
 }
 
-// Position of every boundary row in every input column: bpos[b*k + i].
-__global__ __launch_bounds__(256) void k_win_search(PlanParams p, const int* const* __restrict__ cp,
-                                                    const int* const* __restrict__ ri,
-                                                    const int* __restrict__ wcols, const int* __restrict__ wfirst,
-                                                    int n_bounds, const int* __restrict__ bcol,
-                                                    const int* __restrict__ brow, int* __restrict__ bpos) {
+// Position of every boundary row in every input column: bpos[b*k + i] = the first
+// entry of input i's column at or after boundary row b.
+// Whether window column c's boundaries are found by one ordered pass over its rows
+// (k_win_search_lin) rather than a binary search per (boundary, input): when each
+// input holds 1024..8192 rows of the column on average (shorter: a wavefront mostly
+// waits on the loads that start each input; longer: a block's sequential pass over
+// its inputs outlasts the searches).
+__device__ __forceinline__ bool win_search_linear(long long u, int k) {
+  return u >= 1024LL * k && u <= 8192LL * k;
+}
+
+// One binary search per (boundary, input), for the columns that do not take the
+// ordered pass.
+__global__ __launch_bounds__(256) void k_win_search_bs(PlanParams p, const int* const* __restrict__ cp,
+                                                       const int* const* __restrict__ ri,
+                                                       const int* __restrict__ wcols, const int* __restrict__ wfirst,
+                                                       const int* __restrict__ u, int n_bounds,
+                                                       const int* __restrict__ bcol, const int* __restrict__ brow,
+                                                       int* __restrict__ bpos) {
   const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
   if (t >= (long long)n_bounds * p.k) return;
   const int b = (int)(t / p.k), i = (int)(t - (long long)b * p.k);
   const int c = bcol[b];
   const int j = wcols[c];
+  if (win_search_linear(u[j], p.k)) return;  // k_win_search_lin's column
   const int* col = cp[i];
   const int s = col[j], e = col[j + 1];
   const int first = wfirst[c] + c, last = wfirst[c + 1] + c;
@@ -294,6 +308,63 @@ __global__ __launch_bounds__(256) void k_win_search(PlanParams p, const int* con
   else if (b == last) pos = e;
   else pos = lower_bound_rows(ri[i], s, e, brow[b]);
   bpos[t] = pos;
+}
+
+// The ordered pass: block (c, g) takes inputs 16 g .. 16 g + 15 of window column c, a
+// wavefront one input at a time.  The boundaries are the equal row splits
+// B_q = floor(q m / P), so a row's window is arithmetic: the largest q < P with
+// q m <= (row + 1) P - 1 (a floating-point estimate, corrected by exact integer
+// compares).  Along an input the window index of its rows is kept as a running
+// maximum (so it never decreases, whatever the input), and boundary q's position is
+// the first row whose window reaches q; boundaries after the last row's window are at
+// the segment end.  Every boundary of the input is written once.
+constexpr int WSL_THREADS = 256;
+constexpr int WSL_GROUP = 16;
+__global__ __launch_bounds__(WSL_THREADS) void k_win_search_lin(PlanParams p, const int* const* __restrict__ cp,
+                                                                const int* const* __restrict__ ri,
+                                                                const int* __restrict__ wcols,
+                                                                const int* __restrict__ wfirst,
+                                                                const int* __restrict__ u, int* __restrict__ bpos) {
+  const int groups = (p.k + WSL_GROUP - 1) / WSL_GROUP;
+  const int c = blockIdx.x / groups, g = blockIdx.x - c * groups;
+  const int j = wcols[c];
+  if (!win_search_linear(u[j], p.k)) return;  // k_win_search_bs's column
+  const int first = wfirst[c] + c;
+  const int P = wfirst[c + 1] - wfirst[c];
+  const long long k = p.k, m = p.m;
+  const double inv_m = 1.0 / (double)m;
+  const int lane = lane_id();
+  const int i1 = min(p.k, (g + 1) * WSL_GROUP);
+  for (int i = g * WSL_GROUP + (threadIdx.x >> 6); i < i1; i += WSL_THREADS / 64) {
+    const int* col = cp[i];
+    const int s = col[j], e = col[j + 1];
+    const int* r = ri[i];
+    int* out = bpos + (long long)first * k + i;  // boundary q at out[q * k]
+    if (lane == 0) {
+      out[0] = s;
+      out[(long long)P * k] = e;
+    }
+    int prevw = 0;  // window of the row before the chunk (0 before the first row)
+    for (int base = s; base < e; base += 64) {
+      const int idx = base + lane;
+      int w = -1;
+      if (idx < e) {
+        const long long lim = ((long long)gload<int>((long long)(r + idx)) + 1) * P - 1;
+        long long q = (long long)((double)lim * inv_m);
+        q = q < 0 ? 0 : q > P - 1 ? P - 1 : q;
+        while (q > 0 && q * m > lim) --q;
+        while (q < P - 1 && (q + 1) * m <= lim) ++q;
+        w = (int)q;
+      }
+      const int wm = max(wave_scan_max(w), prevw);
+      const int up = __shfl_up(wm, 1, 64);
+      const int wprev = lane == 0 ? prevw : up;
+      if (idx < e)
+        for (int q = wprev + 1; q <= wm; ++q) out[(long long)q * k] = idx;
+      prevw = readlane(wm, 63);
+    }
+    for (int q = prevw + 1 + lane; q <= P - 1; q += 64) out[(long long)q * k] = e;
+  }
 }
 
 // Input count of every window; windows with more than cap_in entries and more than
@@ -308,8 +379,9 @@ __global__ __launch_bounds__(256) void k_win_count(PlanParams p, int n_windows, 
   const int* lo = bpos + (long long)b * p.k;
   const int* hi = lo + p.k;
   long long cnt = 0;
-  for (int i = 0; i < p.k; ++i) cnt += hi[i] - lo[i];
+  for (int i = 0; i < p.k; ++i) cnt += max(hi[i] - lo[i], 0);  // (inverted only for an unsorted input)
   const int width = brow[b + 1] - brow[b];
+  atomicMax(&sum->max_span, width);
   int pieces = 1;
   if (cnt > p.cap_in && width > p.cap_in) {
     const double target = (double)p.cap_in * (double)p.win_fill;
@@ -533,12 +605,15 @@ void launch_win_fill(const PlanParams& p, int n_wcols, const int* d_wfirst, int*
 }
 
 void launch_win_search(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
-                       const int* d_wfirst, int n_bounds, const int* d_bcol, const int* d_brow, int* d_bpos,
-                       hipStream_t s) {
+                       const int* d_wfirst, const int* d_u, int n_wcols, int n_bounds, const int* d_bcol,
+                       const int* d_brow, int* d_bpos, hipStream_t s) {
+  if (n_wcols == 0 || p.k == 0) return;
+  const long long groups = (p.k + WSL_GROUP - 1) / WSL_GROUP;
+  k_win_search_lin<<<(unsigned)(n_wcols * groups), WSL_THREADS, 0, s>>>(p, d_cp, d_ri, d_wcols, d_wfirst, d_u,
+                                                                         d_bpos);
   const long long work = (long long)n_bounds * p.k;
-  if (work == 0) return;
-  k_win_search<<<grid_for(work, 256), 256, 0, s>>>(p, d_cp, d_ri, d_wcols, d_wfirst, n_bounds, d_bcol, d_brow,
-                                                   d_bpos);
+  k_win_search_bs<<<grid_for(work, 256), 256, 0, s>>>(p, d_cp, d_ri, d_wcols, d_wfirst, d_u, n_bounds, d_bcol,
+                                                      d_brow, d_bpos);
 }
 
 void launch_win_count(const PlanParams& p, int n_windows, const int* d_win_c, const int* d_brow, const int* d_bpos,

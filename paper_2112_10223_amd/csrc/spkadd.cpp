@@ -258,6 +258,7 @@ struct spkadd_plan_s {
   int binoff[NBINS + 1] = {0};
   // windows
   int n_wcols = 0, n_windows = 0, levels = 0;
+  int max_span = 0;  // widest window (rows)
   int* d_wfirst = nullptr;
   int* d_win_c = nullptr;
   int* d_brow = nullptr;
@@ -359,6 +360,8 @@ int ktop_of(int k) {
 }
 
 bool layout_bin(const spkadd_plan_s* p, int b, bool numeric, KArgs& a);
+bool wg_bitmap_bin(const spkadd_plan_s* p, int b);
+void wg_bitmap_layout(const spkadd_plan_s* p, bool numeric, KArgs& a);
 
 spkadd_status check_lds(spkadd_plan_s* p) {
   const int lmax = max_lds_bytes();
@@ -368,7 +371,12 @@ spkadd_status check_lds(spkadd_plan_s* p) {
     for (int numeric = 0; numeric < 2; ++numeric) {
       KArgs a{};
       const bool pipe = layout_bin(p, b, numeric != 0, a);
-      const long long bytes = (long long)a.slice_bytes * (pipe ? PIPE_WAVES_PER_BLOCK : bin_units_per_block(b));
+      long long bytes = (long long)a.slice_bytes * (pipe ? PIPE_WAVES_PER_BLOCK : bin_units_per_block(b));
+      if (wg_bitmap_bin(p, b)) {
+        KArgs ab{};
+        wg_bitmap_layout(p, numeric != 0, ab);
+        if (ab.slice_bytes > bytes) bytes = ab.slice_bytes;
+      }
       if (bytes > lmax)
         return set_error(SPKADD_ERR_UNSUPPORTED,
                          "bin %d needs %lld bytes of LDS (k=%d, table %d slots); the device has %d", b, bytes, p->k,
@@ -474,9 +482,10 @@ spkadd_status build_windows(spkadd_plan_s* p, hipStream_t s) {
   }
   {
     TraceScope t(p, "win_search", s);
-    launch_win_search(p->pp, p->d_cp, p->d_ri, wcols, p->d_wfirst, W + nwc, p->d_bcol, p->d_brow, p->d_bpos, s);
+    launch_win_search(p->pp, p->d_cp, p->d_ri, wcols, p->d_wfirst, p->d_u, nwc, W + nwc, p->d_bcol, p->d_brow,
+                      p->d_bpos, s);
   }
-  HIP_TRY(hipMemsetAsync(&p->d_sum->pad, 0, sizeof(int), s));
+  HIP_TRY(hipMemsetAsync(&p->d_sum->pad, 0, 2 * sizeof(int), s));  // pad and max_span
   {
     TraceScope t(p, "win_count", s);
     launch_win_count(p->pp, W, p->d_win_c, p->d_brow, p->d_bpos, p->d_cntin, d_q, p->d_sum, s);
@@ -516,7 +525,7 @@ spkadd_status build_windows(spkadd_plan_s* p, hipStream_t s) {
       TraceScope t(p, "win_refine_search", s);
       launch_win_refine_search(p->pp, p->d_ri, W2 + nwc, bcol2, brow2, bpar, bpiece, d_q, p->d_bpos, bpos2, s);
     }
-    HIP_TRY(hipMemsetAsync(&p->d_sum->pad, 0, sizeof(int), s));
+    HIP_TRY(hipMemsetAsync(&p->d_sum->pad, 0, 2 * sizeof(int), s));  // pad and max_span
     {
       TraceScope t(p, "win_count", s);
       launch_win_count(p->pp, W2, win_c2, brow2, bpos2, cntin2, q2, p->d_sum, s);
@@ -546,6 +555,7 @@ spkadd_status build_windows(spkadd_plan_s* p, hipStream_t s) {
   }
   p->release(d_q, s);
   p->n_windows = W;
+  p->max_span = p->h_sum->max_span;  // of the last level counted (the final windows)
   if ((st = p->alloc(&p->d_win_cnt, W, s))) return st;
   if ((st = p->alloc(&p->d_win_off, W, s))) return st;
   return SPKADD_OK;
@@ -577,12 +587,36 @@ bool layout_bin(const spkadd_plan_s* p, int b, bool numeric, KArgs& a) {
   return false;
 }
 
+// Workgroup units (G1, G2, windows) narrow enough for a bitmap over their row range
+// use it, unless hash tables are asked for (accum_mode, or the degenerate-hash test
+// hook, which is about the tables).
+bool wg_bitmap_bin(const spkadd_plan_s* p, int b) {
+  if (b != BIN_G1 && b != BIN_G2 && b != BIN_WIN) return false;
+  if (p->opts.accum_mode == SPKADD_ACCUM_HASH || p->opts.hash_mode != 0) return false;
+  return b == BIN_WIN || p->m <= bitmap_wg_span_max();
+}
+
+void wg_bitmap_layout(const spkadd_plan_s* p, bool numeric, KArgs& a) {
+  lds_layout_bitmap_wg(numeric, p->dtype == SPKADD_F64 ? 8 : 4, p->k, bitmap_wg_span_max(), p->pp.cap_in, a);
+}
+
 // Launches the symbolic or numeric kernel of bin b.
 hipError_t launch_bin(spkadd_plan_s* p, int b, bool numeric, KArgs& a, hipStream_t s) {
   const int cnt = b == BIN_WIN ? p->n_windows : p->bin_count[b];
   if (cnt == 0) return hipSuccess;
   const bool f64 = p->dtype == SPKADD_F64;
   const int* list = b == BIN_WIN ? nullptr : p->d_list + p->binoff[b];
+  if (wg_bitmap_bin(p, b)) {
+    // workgroup bitmap for every unit at most span_max rows wide; the hash kernel
+    // takes the wider ones (only windows can be wider)
+    KArgs ab = a;
+    wg_bitmap_layout(p, numeric, ab);
+    hipError_t e = launch_bitmap_wg(b, numeric, f64, ab, list, cnt, s);
+    if (e != hipSuccess || b != BIN_WIN || p->max_span <= ab.wg_span_max) return e;
+    layout_bin(p, b, numeric, a);
+    a.wg_span_max = ab.wg_span_max;
+    return launch_hash(b, numeric, f64, a, list, cnt, s);
+  }
   if (layout_bin(p, b, numeric, a)) {
     // resident wavefronts per CU: LDS-bound, at most 16 (four per SIMD)
     const int block_lds = a.slice_bytes * PIPE_WAVES_PER_BLOCK;

@@ -52,11 +52,12 @@ def test_small_random(seed):
     assert_matches(batch, got, ref, exact_values=values.startswith("int"))
 
 
-def _ragged_batch(seed=5, k=6, m=20000, values="int32f"):
+def _ragged_batch(seed=5, k=6, m=20000, values="int32f", sizes=None):
     """Columns whose sizes span every bin: empty, wave sub-bins, both workgroup
     bins and the window bin."""
-    sizes = [0, 1, 3, 10, 40, 64, 65, 100, 170, 200, 250, 300, 500, 700, 900, 1100, 1500, 2500, 3000, 3500,
-             6000, 9000]
+    if sizes is None:
+        sizes = [0, 1, 3, 10, 40, 64, 65, 100, 170, 200, 250, 300, 500, 700, 900, 1100, 1500, 2500, 3000, 3500,
+                 6000, 9000]
     n = len(sizes) * 3
     per = np.array([sizes[j % len(sizes)] for j in range(n)], dtype=np.float64) / k
     masks_cp = np.zeros((k, n + 1), np.int32)
@@ -86,6 +87,63 @@ def test_forced_bins(force_bin, window_cap):
     st = got[3]
     if force_bin == 2:
         assert st["n_window_cols"] == batch.n - st["n_empty_cols"]
+
+
+@pytest.mark.parametrize("m", [100000, 1 << 20])
+def test_workgroup_bitmap_and_hash_agree(m):
+    """Workgroup units (both workgroup bins, row windows) through the workgroup bitmap
+    (windows and columns at most 2^17 rows wide) and through hash tables only give the
+    same bits and match the oracle.  With m = 2^20 the sparse window columns have
+    windows wider than 2^17 rows, so one launch mixes bitmap and hash windows, and the
+    workgroup-bin columns stay on hash tables; with m = 100000 every workgroup unit
+    takes the bitmap.  The largest columns hold more entries per window than the
+    workgroup's registers (dense windows: every entry adds)."""
+    note(f"workgroup bitmap vs hash m={m}")
+    sizes = [1200, 2000, 2900, 4000, 5000, 9000, 60000, 200000]
+    batch = _ragged_batch(seed=9, k=6, m=m, sizes=sizes)
+    ref = oracle.spkadd(batch)
+    bm = run_gpu(batch, stats=True)
+    hs = run_gpu(batch, _opts(accum_mode=1), stats=True)
+    assert bm[3]["n_window_cols"] > 0 and bm[3]["n_wg_cols"] > 0
+    assert_matches(batch, bm, ref, exact_values=True)
+    for x, y in zip(bm[:3], hs[:3]):
+        assert np.array_equal(x, y)
+    # forced windows with a small capacity: many narrow windows, dense ones too
+    fw = run_gpu(batch, _opts(force_bin=2, window_cap=256), stats=True)
+    assert_matches(batch, fw, ref, exact_values=True)
+    # fp32 values: within the tolerance
+    bf = _ragged_batch(seed=10, k=6, m=m, sizes=sizes, values="f32")
+    assert_matches(bf, run_gpu(bf), oracle.spkadd(bf))
+
+
+def test_workgroup_bitmap_dense_windows():
+    """Windows of at most 256 rows holding more entries than the workgroup's registers
+    (k = 24 inputs, ~80% of rows present in each): every entry adds into the zeroed
+    staging area."""
+    note("workgroup bitmap dense windows")
+    batch = _ragged_batch(seed=11, k=24, m=5000, sizes=[100000, 60000, 3000])
+    u = sum(np.diff(batch.colptr[i]).astype(np.int64) for i in range(batch.k))
+    assert u.max() > 5000 * 24 * 0.6
+    ref = oracle.spkadd(batch)
+    for opts in (_opts(force_bin=2, window_cap=256), _opts(force_bin=2, window_cap=256, accum_mode=1)):
+        got = run_gpu(batch, opts, stats=True)
+        assert got[3]["n_windows"] > batch.n
+        assert_matches(batch, got, ref, exact_values=True)
+
+
+def test_unsorted_input_in_windows_validated():
+    """An input whose rows are not ascending in window columns: SPKADD_FLAG_VALIDATE
+    rejects it in spkadd_plan, before any window is built."""
+    from paper_2112_10223_amd import binding
+    note("unsorted input in windows")
+    b = workloads.er(20000, 4, 3, 3000.0, seed=5, values="int32f")  # u ~ 9000 > cap: window columns
+    rng = np.random.default_rng(3)
+    for j in range(b.n):
+        s, e = int(b.colptr[0, j]), int(b.colptr[0, j + 1])
+        b.rowidx[0][s:e] = rng.permutation(b.rowidx[0][s:e])
+    with pytest.raises(binding.SpkaddError) as err:
+        run_gpu(b, _opts(flags=binding.SPKADD_FLAG_VALIDATE))
+    assert err.value.status == binding.SPKADD_ERR_INVALID
 
 
 def test_sliding_windows_match_plain():
