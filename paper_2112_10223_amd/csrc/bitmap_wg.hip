@@ -183,7 +183,10 @@ __global__ __launch_bounds__(NT) void k_bitmap_wg(KArgs a, const int* __restrict
 
 // ---- host side ----
 
-int bitmap_wg_span_max() { return 1 << 17; }
+// 2^18 rows: 32 KiB of bitmap and 8 KiB of prefix, two workgroups per CU with the
+// staging area (measured on R-MAT windows: 2^17 leaves more windows to the hash
+// kernel, 2^19 halves the resident workgroups; both slower).
+int bitmap_wg_span_max() { return 1 << 18; }
 
 void lds_layout_bitmap_wg(bool numeric, int vbytes, int k, int span_max, int cap, KArgs& a) {
   auto align16 = [](int x) { return (x + 15) & ~15; };

@@ -361,7 +361,7 @@ int ktop_of(int k) {
 
 bool layout_bin(const spkadd_plan_s* p, int b, bool numeric, KArgs& a);
 bool wg_bitmap_bin(const spkadd_plan_s* p, int b);
-void wg_bitmap_layout(const spkadd_plan_s* p, bool numeric, KArgs& a);
+void wg_bitmap_layout(const spkadd_plan_s* p, int b, bool numeric, KArgs& a, bool worst);
 
 spkadd_status check_lds(spkadd_plan_s* p) {
   const int lmax = max_lds_bytes();
@@ -374,7 +374,7 @@ spkadd_status check_lds(spkadd_plan_s* p) {
       long long bytes = (long long)a.slice_bytes * (pipe ? PIPE_WAVES_PER_BLOCK : bin_units_per_block(b));
       if (wg_bitmap_bin(p, b)) {
         KArgs ab{};
-        wg_bitmap_layout(p, numeric != 0, ab);
+        wg_bitmap_layout(p, b, numeric != 0, ab, true);
         if (ab.slice_bytes > bytes) bytes = ab.slice_bytes;
       }
       if (bytes > lmax)
@@ -596,8 +596,14 @@ bool wg_bitmap_bin(const spkadd_plan_s* p, int b) {
   return b == BIN_WIN || p->m <= bitmap_wg_span_max();
 }
 
-void wg_bitmap_layout(const spkadd_plan_s* p, bool numeric, KArgs& a) {
-  lds_layout_bitmap_wg(numeric, p->dtype == SPKADD_F64 ? 8 : 4, p->k, bitmap_wg_span_max(), p->pp.cap_in, a);
+// The bitmap is sized for the widest unit of the bin (rounded up to a power of two,
+// at most bitmap_wg_span_max()); worst: the largest it can be (before the windows exist).
+void wg_bitmap_layout(const spkadd_plan_s* p, int b, bool numeric, KArgs& a, bool worst = false) {
+  const int cap = bitmap_wg_span_max();
+  const long long need = worst ? cap : b == BIN_WIN ? p->max_span : p->m;
+  int span = 1024;
+  while (span < need && span < cap) span <<= 1;
+  lds_layout_bitmap_wg(numeric, p->dtype == SPKADD_F64 ? 8 : 4, p->k, span, p->pp.cap_in, a);
 }
 
 // Launches the symbolic or numeric kernel of bin b.
@@ -610,7 +616,7 @@ hipError_t launch_bin(spkadd_plan_s* p, int b, bool numeric, KArgs& a, hipStream
     // workgroup bitmap for every unit at most span_max rows wide; the hash kernel
     // takes the wider ones (only windows can be wider)
     KArgs ab = a;
-    wg_bitmap_layout(p, numeric, ab);
+    wg_bitmap_layout(p, b, numeric, ab);
     hipError_t e = launch_bitmap_wg(b, numeric, f64, ab, list, cnt, s);
     if (e != hipSuccess || b != BIN_WIN || p->max_span <= ab.wg_span_max) return e;
     layout_bin(p, b, numeric, a);
