@@ -320,6 +320,8 @@ def main() -> int:
     ap.add_argument("--no-trace", action="store_true", help="time without per-kernel events")
     ap.add_argument("--trace-steps", type=int, default=3, help="untimed steps with every launch traced")
     ap.add_argument("--tune", action="store_true", help="autotune the launch parameters on the workload first")
+    ap.add_argument("--unsorted-out", action="store_true",
+                    help="rows of each output column in any order (hash accumulators skip their sort)")
     ap.add_argument("--batched", type=int, default=400,
                     help="requests of the batched-vs-plain measurement (0 = skip)")
     args = ap.parse_args()
@@ -349,8 +351,9 @@ def main() -> int:
     dtype = binding.SPKADD_F64 if f64 else binding.SPKADD_F32
     # timed steps record HIP events around the numeric launches only (the dominant
     # kernels); a separate untimed pass traces every launch for the phase breakdown
-    opts = binding.make_opts(flags=0 if args.no_trace else binding.SPKADD_FLAG_TRACE_NUMERIC)
-    opts_all = binding.make_opts(flags=binding.SPKADD_FLAG_TRACE)
+    order = binding.SPKADD_FLAG_UNSORTED_OUT if args.unsorted_out else 0
+    opts = binding.make_opts(flags=order | (0 if args.no_trace else binding.SPKADD_FLAG_TRACE_NUMERIC))
+    opts_all = binding.make_opts(flags=order | binding.SPKADD_FLAG_TRACE)
     tuned = None
     if args.tune:  # the autotuner on this workload; the timed steps then use its choice
         best, rep, trials = binding.tune(m, cps, ris, vas, dtype, reps=5)
@@ -482,7 +485,8 @@ def main() -> int:
         "dtype": "f64" if f64 else "f32",
         "data": "synthetic (seeded generator; paper's R-MAT family, no public datasets)",
         "config": {"workload": f"{args.workload}: {desc}", "k": k, "m": m, "n": n, "nnz_in": nnz_in,
-                   "nnz_out": nnz_out, "parallelism": "single GPU"},
+                   "nnz_out": nnz_out, "parallelism": "single GPU",
+                   "output_order": "any" if args.unsorted_out else "sorted"},
         "hbm_gbps_alg_step": round(b_alg / (ms_per_step * 1e-3) / 1e9, 1),
         "hbm_frac_alg_step": round(b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "phase_ms": {kk: round(v, 4) for kk, v in phase_ms.items()},

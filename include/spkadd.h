@@ -64,6 +64,9 @@ typedef enum spkadd_dtype { SPKADD_F32 = 0, SPKADD_F64 = 1 } spkadd_dtype;
 #define SPKADD_FLAG_VALIDATE 1u /* check every input on the device in spkadd_plan */
 #define SPKADD_FLAG_TRACE 2u    /* time every kernel launch with HIP events */
 #define SPKADD_FLAG_TRACE_NUMERIC 4u /* time only the launches of spkadd_numeric */
+#define SPKADD_FLAG_UNSORTED_OUT 8u  /* the rows of each output column may come in any order: the hash
+                                        accumulators skip their sort (the paper's "if sorted output is
+                                        desired", Algorithm 5); bitmap accumulators are sorted anyway */
 
 /* opts.force_bin: test hook that routes columns to one accumulator family */
 #define SPKADD_BIN_AUTO (-1)

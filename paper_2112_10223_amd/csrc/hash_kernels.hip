@@ -128,8 +128,8 @@ __global__ __launch_bounds__(256) void k_num_wave(KArgs a, const int* __restrict
     if (lane == 0) atomicOr(a.err, ERR_COUNT);
     if (c > cnt) c = cnt;
   }
-  V* vs = nullptr;
-  const int in0 = wave_radix_sort<V>(K, Vt, K + TS / 2, Vt + TS / 2, c, 0, ceil_log2(a.m), hist, match, &vs);
+  V* vs = Vt;
+  const int in0 = a.unsorted ? 1 : wave_radix_sort<V>(K, Vt, K + TS / 2, Vt + TS / 2, c, 0, ceil_log2(a.m), hist, match, &vs);
   const int* ks = in0 ? K : K + TS / 2;
   int* outr = a.out_r + o0;
   V* outv = (V*)a.out_v + o0;
@@ -307,9 +307,11 @@ __global__ __launch_bounds__(NT) void k_hash_wg(KArgs a, const int* __restrict__
     if (tid == 0) atomicOr(a.err, ERR_COUNT);
     if (c > cnt) c = cnt;
   }
-  V* vs = nullptr;
-  const int in0 = block_radix_sort<NT, V>(K, Vt, K + TS / 2, Vt + TS / 2, c, rlo, ceil_log2(rhi - rlo),
-                                          (int*)(smem + a.off_hist), (u64*)(smem + a.off_match), red, &vs);
+  V* vs = Vt;
+  const int in0 = a.unsorted ? 1
+                             : block_radix_sort<NT, V>(K, Vt, K + TS / 2, Vt + TS / 2, c, rlo, ceil_log2(rhi - rlo),
+                                                       (int*)(smem + a.off_hist), (u64*)(smem + a.off_match), red,
+                                                       &vs);
   const int* ks = in0 ? K : K + TS / 2;
   int* outr = a.out_r + o0;
   V* outv = (V*)a.out_v + o0;

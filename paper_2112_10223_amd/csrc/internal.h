@@ -97,6 +97,7 @@ struct KArgs {
   // workgroup units: units at most wg_span_max rows wide go to the bitmap kernel (the
   // hash kernel skips them); wg_cap = its staging capacity in output entries
   int wg_span_max, wg_cap;
+  int unsorted;           // numeric: 1 = write each column in table order (no sort)
 };
 
 // ---- plan kernels (plan_kernels.hip) ----

@@ -905,6 +905,7 @@ spkadd_status spkadd_numeric(spkadd_plan_t p, const void* const* values, int32_t
   }
   KArgs a = base_args(p);
   a.alpha_q = p->alpha_num_q;
+  a.unsorted = (p->opts.flags & SPKADD_FLAG_UNSORTED_OUT) ? 1 : 0;
   a.colptr_c = p->colptr_c;
   a.out_r = rowidx_c;
   a.out_v = values_c;

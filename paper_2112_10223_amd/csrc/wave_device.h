@@ -244,6 +244,11 @@ __device__ __forceinline__ void num_unit(const KArgs& a, unsigned char* base, in
     nc = 0;  // write nothing for this unit
   }
   if (!live) nc = 0;  // a replayed unit writes nothing
+  if (a.unsorted) {  // (uniform) table order
+    wave_sync();
+    write_column<E, V>(a, o0, nc, K, Vt);
+    return;
+  }
   mn = wave_total_min(mn);
   mx = wave_total_max(mx);
   const int bits = mx >= mn ? ceil_log2(mx - mn + 1) : 0;

@@ -146,6 +146,39 @@ def test_unsorted_input_in_windows_validated():
     assert err.value.status == binding.SPKADD_ERR_INVALID
 
 
+def _sorted_columns(got):
+    """(colptr, rows, values) with each column's entries ordered by row."""
+    colptr, rows, vals = got[:3]
+    rows = rows.copy()
+    vals = vals.copy()
+    for j in range(len(colptr) - 1):
+        s, e = int(colptr[j]), int(colptr[j + 1])
+        o = np.argsort(rows[s:e], kind="stable")
+        rows[s:e] = rows[s:e][o]
+        vals[s:e] = vals[s:e][o]
+    return colptr, rows, vals
+
+
+@pytest.mark.parametrize("accum_mode", [0, 1])
+def test_unsorted_output(accum_mode):
+    """SPKADD_FLAG_UNSORTED_OUT: every column holds the same (row, value) pairs as the
+    sorted output, in any order (the hash accumulators skip their sort; the bitmap
+    ones stay sorted).  Wave bins, both workgroup bins and row windows, hash tables
+    only (accum_mode 1) and the default choice."""
+    from paper_2112_10223_amd import binding
+    note(f"unsorted output accum_mode={accum_mode}")
+    batches = [_ragged_batch(seed=12, k=6, m=1 << 20), workloads.er(300000, 400, 8, 30.0, seed=13, values="int32f")]
+    for batch in batches:
+        ref = oracle.spkadd(batch)
+        for extra in ({}, {"force_bin": 2, "window_cap": 256}):
+            got = run_gpu(batch, _opts(flags=binding.SPKADD_FLAG_UNSORTED_OUT, accum_mode=accum_mode, **extra))
+            assert_matches(batch, _sorted_columns(got), ref, exact_values=True)
+    # the flag changes nothing where the result is sorted anyway
+    b = workloads.er(65536, 300, 32, 16.0, seed=14, values="int32f")
+    plain = run_gpu(b)
+    assert all(np.array_equal(x, y) for x, y in zip(plain, run_gpu(b, _opts(flags=binding.SPKADD_FLAG_UNSORTED_OUT))))
+
+
 def test_sliding_windows_match_plain():
     """Forcing the sliding hash must reproduce the plain result bit for bit on
     colptr / rowidx (Algorithms 7-8 change only where the table lives)."""
