@@ -309,6 +309,41 @@ def cpu_baseline(batch, max_cols: int | None = None):
                       f"of the same inputs ({nnz_in} input nnz), {dt:.2f} s"}
 
 
+def cpu_baseline_all_cores(batch):
+    """The same oracle over column chunks on every core of the host's share (threads:
+    the oracle's C routine runs without the interpreter lock)."""
+    import concurrent.futures as cf
+    import oracle
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    chunks = np.array_split(np.arange(batch.n, dtype=np.int64), threads * 4)
+    oracle.spkadd(batch, cols=chunks[0][:1])  # library loaded before timing
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda c: oracle.spkadd(batch, cols=c), chunks))
+    dt = time.perf_counter() - t0
+    return {"value": batch.nnz_in / dt, "unit": "input nnz/s", "cores": threads, "kind": "oracle",
+            "sample": f"the oracle on all {batch.n} columns in {len(chunks)} chunks over {threads} threads, {dt:.2f} s"}
+
+
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Achievable HBM bandwidth: a device-to-device copy of nbytes (read + write),
+    best of reps, GB/s."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    return round(2 * nbytes / (best * 1e-3) / 1e9, 1)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -383,7 +418,13 @@ def main() -> int:
 
     host_s = {"plan": 0.0, "symbolic": 0.0, "numeric": 0.0}
 
+    step_events = []  # (end of the previous step, end of this one) on the launch stream
+
     def step(o):
+        if step_events is not None and collect_steps[0]:
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record()
+            step_events.append(ev)
         t_a = time.perf_counter()
         p = binding.spkadd_plan(m, n, pcp, pri, dtype, o, stream)
         t_b = time.perf_counter()
@@ -394,7 +435,13 @@ def main() -> int:
         host_s["plan"] += t_b - t_a
         host_s["symbolic"] += t_c - t_b
         host_s["numeric"] += t_d - t_c
+        if collect_steps[0]:
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record()
+            step_events.append(ev)
         return p
+
+    collect_steps = [False]
 
     def run(nsteps, o, collect):
         """nsteps steps; a plan is freed (after reading its trace) once the next one is
@@ -415,10 +462,16 @@ def main() -> int:
     torch.cuda.synchronize()
     for kk in host_s:
         host_s[kk] = 0.0
+    collect_steps[0] = True
     t0 = time.perf_counter()
     last, traces = run(args.steps, opts, not args.no_trace)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    collect_steps[0] = False
+    # per-step device time: from the end of the previous step's launches to the end of
+    # this step's on the stream (a step starts when the device reaches its first launch)
+    step_ms = [step_events[2 * i].elapsed_time(step_events[2 * i + 1]) for i in range(len(step_events) // 2)]
+    step_ms_q = {f"p{q}": round(float(np.percentile(step_ms, q)), 4) for q in (10, 50, 90)} if step_ms else None
     if not args.no_trace:
         traces.append(binding.spkadd_trace(last))
     last.free()
@@ -470,6 +523,7 @@ def main() -> int:
                     "units_per_launch": int(sel.sum())}
 
     b_alg = (8 + vbytes) * nnz_in + (4 + vbytes) * nnz_out + 12 * k * (n + 1) + 12 * (n + 1)
+    b_min = (4 + vbytes) * (nnz_in + nnz_out) + 4 * (k + 1) * (n + 1)  # every byte read or written once
     value = nnz_in / (ms_per_step * 1e-3)
     out = {
         "metric": METRIC,
@@ -489,6 +543,9 @@ def main() -> int:
                    "output_order": "any" if args.unsorted_out else "sorted"},
         "hbm_gbps_alg_step": round(b_alg / (ms_per_step * 1e-3) / 1e9, 1),
         "hbm_frac_alg_step": round(b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "hbm_gbps_min_step": round(b_min / (ms_per_step * 1e-3) / 1e9, 1),
+        "step_ms": step_ms_q,
+        "copy_gbps": copy_bandwidth(),
         "phase_ms": {kk: round(v, 4) for kk, v in phase_ms.items()},
         "host_call_ms": host_call_ms,
         "kernel_ms": {kk: round(v, 5) for kk, v in sorted(all_ms.items())},
@@ -502,6 +559,7 @@ def main() -> int:
         out["served"], out["batched"] = measure_batched(args.batched)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(batch)
+        out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(batch)
     print(json.dumps(out))
     return 0
 
