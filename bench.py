@@ -117,7 +117,8 @@ def measure_served(reqs, plain_service_s: float, plain_one, load: float = 0.8, s
                    server_config: dict | None = None) -> dict:
     """Poisson arrivals at `load` times the rate one-request plain launches can sustain
     (1 / mean plain service time).  (a) plain: each request at its arrival time, in
-    order, one at a time through plan / symbolic / numeric; (b) served: a submitter
+    order, one at a time through plan / symbolic / numeric; (a') the same on four
+    streams from four host threads; (b) served: a submitter
     thread hands each request to the serving loop at its arrival time.  Latency =
     completion - arrival; p50 / p99 over all requests."""
     import threading
@@ -146,6 +147,34 @@ def measure_served(reqs, plain_service_s: float, plain_one, load: float = 0.8, s
         torch.cuda.synchronize()
         lat_plain.append(time.perf_counter() - t0 - a)
     span_plain = time.perf_counter() - t0
+    # (a') plain on 4 streams: 4 host threads, each with its own stream, take the
+    # requests in arrival order as they become free
+    lat_p4 = [0.0] * len(reqs)
+    nxt = [0]
+    lock = threading.Lock()
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+
+    def worker(st):
+        sp = binding._stream_ptr(st)
+        while True:
+            with lock:
+                i = nxt[0]
+                nxt[0] += 1
+            if i >= len(reqs):
+                return
+            wait_until(t0, arrivals[i])
+            plain_one(reqs[i], sp)
+            st.synchronize()
+            lat_p4[i] = time.perf_counter() - t0 - arrivals[i]
+
+    ths = [threading.Thread(target=worker, args=(st,)) for st in streams]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    span_p4 = time.perf_counter() - t0
     # (b) the serving loop
     cols = max(int(q["colptr_c"].shape[0]) for q in reqs)
     sc = dict(SERVER_CONFIG, **(server_config or {}))
@@ -191,6 +220,7 @@ def measure_served(reqs, plain_service_s: float, plain_one, load: float = 0.8, s
     return {"arrival_rate_per_s": round(rate, 1), "load_vs_plain": load, "requests": len(reqs), "server": sc,
             "plain": {"p50_ms": pct(lat_plain, 50), "p99_ms": pct(lat_plain, 99),
                       "nnz_per_s": nnz_in / span_plain},
+            "plain_4_streams": {"p50_ms": pct(lat_p4, 50), "p99_ms": pct(lat_p4, 99), "nnz_per_s": nnz_in / span_p4},
             "served": {"p50_ms": pct(lat_srv, 50), "p99_ms": pct(lat_srv, 99), "nnz_per_s": nnz_in / span_srv,
                        "one_request_path": int(sum(paths)), "p50_admission_wait_ms": pct(qwait, 50),
                        "p50_run_ms": pct(run, 50), "timed_region": timed},
@@ -222,11 +252,12 @@ def measure_batched(count: int = 120, batch_size: int = 40, max_nnz: int = 1 << 
                          values_c=torch.empty(cap, dtype=torch.float32, device=dev), cap_c=cap, keep=(cps, ris, vas)))
     stream = binding._stream_ptr(None)
 
-    def plain_one(q):
+    def plain_one(q, s=None):
+        s = stream if s is None else s
         p = binding.spkadd_plan(q["m"], q["colptr_c"].shape[0] - 1, q["colptrs"], q["rowidxs"], binding.SPKADD_F32,
-                                None, stream)
-        binding.spkadd_symbolic(p, q["colptr_c"], stream)
-        binding.spkadd_numeric(p, q["values"], q["rowidx_c"], q["values_c"], stream)
+                                None, s)
+        binding.spkadd_symbolic(p, q["colptr_c"], s)
+        binding.spkadd_numeric(p, q["values"], q["rowidx_c"], q["values_c"], s)
         p.free()
 
     def plain_all():
@@ -284,7 +315,7 @@ def measure_batched(count: int = 120, batch_size: int = 40, max_nnz: int = 1 << 
         bt.close()
     # served: each entry a server configuration and an offered load (times what
     # one-request launches sustain)
-    cases = serve if isinstance(serve, list) else [{"load": 0.8}, {"load": 1.5}] if serve else []
+    cases = serve if isinstance(serve, list) else [{"load": 0.5}, {"load": 0.8}, {"load": 1.5}] if serve else []
     served = [measure_served(reqs, times["plain"] / len(reqs), plain_one, load=c.get("load", 0.8),
                              server_config={k: v for k, v in c.items() if k != "load"}) for c in cases]
     return served, {"requests": len(reqs), "batch_size": batch_size, "input_nnz": int(nnz_in),
