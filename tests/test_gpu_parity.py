@@ -146,6 +146,40 @@ def test_unsorted_input_in_windows_validated():
     assert err.value.status == binding.SPKADD_ERR_INVALID
 
 
+@pytest.mark.parametrize("seed", range(16))
+def test_random_options(seed):
+    """Seeded random shapes and option combinations (bins forced or automatic, window
+    capacity, wave limit, accumulator choice, bin merging, unsorted output, fp32 and
+    fp64), each against the oracle: colptr and rows exact, values exact for integer
+    inputs (per column as sets when the output order is free)."""
+    from paper_2112_10223_amd import binding
+    rng = np.random.default_rng(1000 + seed)
+    m = int(rng.choice([1, 7, 300, 5000, 65536, 131072, 300000, 1 << 20]))
+    n = int(rng.integers(1, 400))
+    k = int(rng.choice([1, 2, 3, 8, 32, 65, 130]))
+    d = float(min(m * 0.8, rng.choice([0.5, 4.0, 20.0, 200.0, 2000.0]) / max(1, k // 8)))
+    values = str(rng.choice(["int32f", "int64f", "f32", "f64"]))
+    kw = {}
+    if rng.random() < 0.4:
+        kw["force_bin"] = int(rng.choice([0, 1, 2]))
+    if rng.random() < 0.4:
+        kw["window_cap"] = int(rng.choice([64, 256, 1000, 4096]))
+    if rng.random() < 0.3:
+        kw["wave_max"] = int(rng.choice([256, 512, 768]))
+    kw["accum_mode"] = int(rng.choice([0, 0, 1, 2]))
+    kw["wave_merge"] = int(rng.integers(0, 2))
+    unsorted = rng.random() < 0.3
+    if unsorted:
+        kw["flags"] = binding.SPKADD_FLAG_UNSORTED_OUT
+    note(f"random options seed={seed} m={m} n={n} k={k} d={d:.2f} values={values} {kw}")
+    batch = workloads.er(m, n, k, d, seed=77 + seed, values=values)
+    ref = oracle.spkadd(batch)
+    got = run_gpu(batch, _opts(**kw))
+    if unsorted:
+        got = _sorted_columns(got)
+    assert_matches(batch, got, ref, exact_values=values.startswith("int"))
+
+
 def _sorted_columns(got):
     """(colptr, rows, values) with each column's entries ordered by row."""
     colptr, rows, vals = got[:3]
