@@ -149,6 +149,21 @@ unsigned grid_for(const spkadd_batch_s* b, int slice_bytes, int* block_lds) {
   return (unsigned)(b->n_cu * bpc);
 }
 
+// The workgroup-sized columns of a pass (every run: whether a run has any is known on
+// the device only).
+int enqueue_wg(spkadd_batch_s* b, bool numeric, hipStream_t s) {
+  const bool f64 = b->dtype == SPKADD_F64;
+  KArgs a{};
+  a.err = b->args.err;
+  a.dummy = b->args.dummy;
+  a.alpha_q = 512;
+  lds_layout_bitmap_wg(numeric, f64 ? 8 : 4, 64, BATCH_WG_SPAN, BATCH_WG_U, a);
+  int bpc = max_lds_bytes() / a.slice_bytes;
+  bpc = bpc < 1 ? 1 : bpc > 8 ? 8 : bpc;
+  launch_batch_wg(numeric, f64, b->args, a, (unsigned)(b->n_cu * bpc), s);
+  return 1;
+}
+
 // The whole run after the request-table upload.  Returns the kernels enqueued.
 int enqueue_run(spkadd_batch_s* b, const ShapeKey& key, hipStream_t s) {
   int kernels = 0;
@@ -160,6 +175,7 @@ int enqueue_run(spkadd_batch_s* b, const ShapeKey& key, hipStream_t s) {
       launch_batch_scan(b->args, s);
       ++kernels;
     }
+    kernels += enqueue_wg(b, numeric != 0, s);
     if (key.fused) {
       // one launch: the slice is the largest of the slots that can occur
       KArgs a{};

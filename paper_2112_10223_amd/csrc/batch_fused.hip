@@ -3,6 +3,7 @@
 // slot it saves the launches and the per-slot tails (the waves of a slot kernel wait
 // for its slowest chunk) at the price of the largest slot's registers and LDS.
 #include "batch_device.h"
+#include "bitmap_wg_device.h"
 
 namespace spk {
 
@@ -54,6 +55,47 @@ __global__ __launch_bounds__(64 * PIPE_WAVES_PER_BLOCK) void k_batch_fused(Batch
       before += nchunks;
     }
   }
+}
+
+// Persistent, one launch per pass: workgroup w of W takes the columns w, w + W, ...
+// of the workgroup slot, each through the workgroup bitmap over its request's rows.
+template <bool NUM, typename V>
+__global__ __launch_bounds__(BATCH_WG_THREADS) void k_batch_wg(BatchArgs b, KArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ long long red[BATCH_WG_THREADS / 64 + 1];
+  __shared__ int info;
+  const int count = b.slotoff[BSLOTS + 1 + BSLOT_WG];
+  const int off = b.slotoff[BSLOT_WG];
+  for (int item = xcd_remap(blockIdx.x, gridDim.x); item < count; item += gridDim.x) {
+    const int g = b.list[off + item];
+    const int r = b.req_of[g];
+    const BatchReq& q = b.reqs[r];
+    if (NUM && b.status[r] != 0) continue;  // uniform: the request's outcome is not OK
+    KArgs ta = a;
+    ta.cp = q.cp;
+    ta.ri = q.ri;
+    ta.va = q.va;
+    ta.m = q.m;
+    ta.n = q.n;
+    ta.k = q.k;
+    int ktop = 0;  // largest power of two <= k - 1
+    while ((ktop << 1) <= q.k - 1) ktop = ktop ? ktop << 1 : 1;
+    ta.ktop = q.k > 1 ? ktop : 0;
+    ta.colcnt = b.colcnt + q.col_base;
+    ta.colptr_c = q.colptr_c;
+    ta.out_r = q.out_r;
+    ta.out_v = q.out_v;
+    bitmap_wg_unit<BATCH_WG_THREADS, BATCH_WG_U / BATCH_WG_THREADS, NUM, false, V>(ta, smem, red, &info, 0,
+                                                                                 g - q.col_base, 0, 0, q.m);
+    __syncthreads();  // the next column rewrites the LDS this one may still read
+  }
+}
+
+void launch_batch_wg(bool numeric, bool f64, const BatchArgs& b, const KArgs& a, unsigned blocks, hipStream_t s) {
+  const size_t lds = (size_t)a.slice_bytes;
+  if (!numeric) k_batch_wg<false, float><<<blocks, BATCH_WG_THREADS, lds, s>>>(b, a);
+  else if (f64) k_batch_wg<true, double><<<blocks, BATCH_WG_THREADS, lds, s>>>(b, a);
+  else k_batch_wg<true, float><<<blocks, BATCH_WG_THREADS, lds, s>>>(b, a);
 }
 
 int batch_fused_blocks_per_cu(bool numeric, bool f64, size_t lds) {

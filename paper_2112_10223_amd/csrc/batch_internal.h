@@ -30,7 +30,14 @@ struct BatchHdr {
 constexpr int BSLOT_EMPTY = 0;
 constexpr int BSLOT_LARGE = 1;
 constexpr int BSLOT_WAVE = 2;  // + 2 * (wave bin index) + (1 for the bitmap)
-constexpr int BSLOTS = BSLOT_WAVE + 2 * NWAVE_BINS;
+// Workgroup-sized columns (1024 < u_j <= BATCH_WG_U) of requests with at most
+// BATCH_WG_SPAN rows: one workgroup bitmap each (larger columns are left to the
+// one-request path).
+constexpr int BSLOT_WG = BSLOT_WAVE + 2 * NWAVE_BINS;
+constexpr int BSLOTS = BSLOT_WG + 1;
+constexpr int BATCH_WG_U = 4096;
+constexpr int BATCH_WG_SPAN = 1 << 17;
+constexpr int BATCH_WG_THREADS = 256;
 constexpr int BATCH_CHUNK = 16;  // list entries per wavefront task
 
 // Per-request outcome bits (values of SPKADD_REQ_*).
@@ -65,6 +72,9 @@ void launch_batch_wave(int wi, bool numeric, bool f64, bool bm, const BatchArgs&
 // LDS slice (the largest of the slots).
 void launch_batch_fused(bool numeric, bool f64, const BatchArgs& b, const KArgs& a, unsigned blocks, size_t lds,
                         hipStream_t s);
+// The workgroup-sized columns of one pass; `a` holds the common fields and the LDS
+// layout (lds_layout_bitmap_wg for BATCH_WG_SPAN rows, BATCH_WG_U entries, k = 64).
+void launch_batch_wg(bool numeric, bool f64, const BatchArgs& b, const KArgs& a, unsigned blocks, hipStream_t s);
 // Blocks of the fused kernel resident per CU with `lds` bytes of LDS per block (0 if
 // the query fails).
 int batch_fused_blocks_per_cu(bool numeric, bool f64, size_t lds);

@@ -72,6 +72,8 @@ __global__ __launch_bounds__(256) void k_batch_bounds(BatchArgs b) {
       b.colcnt[g] = 0;
       if (u <= 0) {
         slot = BSLOT_EMPTY;
+      } else if (u > 1024 && u <= BATCH_WG_U && q.m <= BATCH_WG_SPAN) {
+        slot = BSLOT_WG;
       } else if (u > 1024) {
         slot = BSLOT_LARGE;
         atomicOr(&b.status[r], REQ_TOO_LARGE);

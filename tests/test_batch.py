@@ -100,7 +100,7 @@ def test_batch_matches_oracle(values, use_graph, fused_cols):
     _check_all(batches, reqs, nnz, st, exact=values.startswith("int"))
     info = bt.info()
     assert info["fused_runs"] == (1 if fused_cols == 0 else 0)
-    assert info["kernels_per_run"] == 7 if fused_cols == 0 else info["kernels_per_run"] > 7
+    assert info["kernels_per_run"] == 9 if fused_cols == 0 else info["kernels_per_run"] > 9
     if use_graph:
         assert info["graphs_captured"] == 1 and info["graph_replays"] == 1
     bt.close()
@@ -182,7 +182,7 @@ def test_batch_too_large_and_capacity():
     from paper_2112_10223_amd import binding
     note("batch too large / capacity")
     small = _random_batches(21, 6, "int32f")
-    big = workloads.er(5000, 10, 4, 400.0, seed=99, values="int32f")  # u about 1600 > 1024
+    big = workloads.er(5000, 10, 4, 1500.0, seed=99, values="int32f")  # u about 6000 > 4096
     batches = small[:3] + [big] + small[3:]
     reqs = _requests(batches)
     # request 1 gets too little room for its output
@@ -200,6 +200,32 @@ def test_batch_too_large_and_capacity():
     assert (reqs[1]["rowidx_c"].cpu().numpy() == -7).all()  # nothing written
     ok = [i for i in range(len(batches)) if i not in (1, 3)]
     _check_all([batches[i] for i in ok], [reqs[i] for i in ok], [nnz[i] for i in ok], [st[i] for i in ok], True)
+    bt.close()
+
+
+@pytest.mark.parametrize("values", ["int32f", "f32", "f64"])
+def test_batch_workgroup_columns(values):
+    """Columns with 1024 < u <= 4096 entries (requests of at most 2^17 rows) are
+    computed inside the batched run by the workgroup bitmap; wider requests or longer
+    columns are reported too large.  Mixed with wave-sized requests."""
+    import torch
+    from paper_2112_10223_amd import binding
+    note(f"batch workgroup columns values={values}")
+    batches = _random_batches(51, 8, values)
+    batches.insert(2, workloads.er(6000, 40, 5, 500.0, seed=52, values=values))     # u ~ 2500
+    batches.insert(5, workloads.er(131072, 30, 12, 300.0, seed=53, values=values))  # u ~ 3600, m = 2^17
+    batches.append(workloads.er(40000, 25, 3, 500.0, seed=54, values=values))       # u ~ 1500
+    too_long = workloads.er(3000, 10, 3, 2000.0, seed=55, values=values)             # u ~ 6000
+    too_wide = workloads.er(140000, 10, 4, 400.0, seed=56, values=values)            # m > 2^17
+    batches += [too_long, too_wide]
+    reqs = _requests(batches)
+    dtype = binding.SPKADD_F64 if values == "f64" else binding.SPKADD_F32
+    bt = _batch(dtype, 32, 20000, 2000)
+    bt.run(reqs, use_graph=True)
+    nnz, st = bt.results()
+    torch.cuda.synchronize()
+    assert st[-2] == binding.SPKADD_REQ_TOO_LARGE and st[-1] == binding.SPKADD_REQ_TOO_LARGE
+    _check_all(batches[:-2], reqs[:-2], nnz[:-2], st[:-2], exact=values.startswith("int"))
     bt.close()
 
 

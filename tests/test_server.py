@@ -56,7 +56,7 @@ def test_server_alone_vs_mix(n_streams, depth):
     from paper_2112_10223_amd import binding
     note(f"server alone vs mix streams={n_streams} depth={depth}")
     targets = _mixed(7, 16)
-    targets.append(workloads.er(4000, 12, 3, 500.0, seed=5, values="int32f"))  # too large for a batch
+    targets.append(workloads.er(20000, 12, 3, 2000.0, seed=5, values="int32f"))  # too large for a batch (u > 4096)
     others = _mixed(8, 40)
     srv = binding.Server(n_streams=n_streams, max_batch=16, max_columns=4096, max_inputs=256, depth=depth)
     alone = []
