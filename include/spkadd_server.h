@@ -16,8 +16,9 @@
  * output memory together stay within the HBM budget.  Inputs must stay valid until
  * the ticket completes.
  *
- * While runs are in flight the server thread polls their completion every few
- * microseconds (one host core busy); idle, it sleeps until a submit.
+ * While runs are in flight, and for 0.5 ms after its last work, the server thread
+ * polls every few microseconds (one host core busy); idle longer, it sleeps until a
+ * submit.  spkadd_server_wait polls its ticket for up to 2 ms before it sleeps.
  */
 #ifndef SPKADD_SERVER_H
 #define SPKADD_SERVER_H

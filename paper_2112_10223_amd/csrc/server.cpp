@@ -206,9 +206,16 @@ bool admit(spkadd_server_s* s, Lane& ln) {
   return true;
 }
 
+// How long the server thread keeps polling after its last work before it sleeps on
+// the condition variable (waking from it costs tens of microseconds), and how long a
+// waiting client polls its ticket before it sleeps.
+constexpr auto kIdleSpin = std::chrono::microseconds(500);
+constexpr auto kWaitSpin = std::chrono::microseconds(2000);
+
 void server_loop(spkadd_server_s* s) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
+  auto last_work = std::chrono::steady_clock::now();
   for (;;) {
     bool progress = false;
     for (Lane& ln : s->lanes) progress |= retire(s, ln);
@@ -223,10 +230,13 @@ void server_loop(spkadd_server_s* s) {
       s->cv_done.notify_all();
       break;
     }
-    if (progress) continue;
-    if (running) {
-      // runs in flight: poll their completion every few microseconds (a timed wait
-      // on the condition variable wakes up far later than asked)
+    if (progress) {
+      last_work = std::chrono::steady_clock::now();
+      continue;
+    }
+    if (running || std::chrono::steady_clock::now() - last_work < kIdleSpin) {
+      // runs in flight, or idle only briefly: poll every few microseconds (a timed
+      // wait on the condition variable wakes up far later than asked)
       lk.unlock();
       const auto t1 = std::chrono::steady_clock::now();
       while (std::chrono::steady_clock::now() - t1 < std::chrono::microseconds(5)) std::this_thread::yield();
@@ -382,6 +392,14 @@ spkadd_status spkadd_server_wait(spkadd_server_t s, uint64_t ticket, spkadd_resu
   auto it = s->tickets.find(ticket);
   if (it == s->tickets.end()) return sfail(SPKADD_ERR_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
   auto done = [&] { return s->tickets[ticket].state == TState::Done; };
+  // poll for a short while first: most tickets complete within it
+  const auto t0 = std::chrono::steady_clock::now();
+  while (!done() && std::chrono::steady_clock::now() - t0 < kWaitSpin &&
+         (timeout_s < 0 || std::chrono::steady_clock::now() - t0 < std::chrono::duration<double>(timeout_s))) {
+    lk.unlock();
+    std::this_thread::yield();
+    lk.lock();
+  }
   if (timeout_s < 0) {
     s->cv_done.wait(lk, done);
   } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) {
