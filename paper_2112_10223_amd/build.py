@@ -56,5 +56,22 @@ def build_library(verbose: bool = False) -> str:
     return LIB_PATH
 
 
+EXAMPLE_SRC = os.path.join(ROOT, "examples", "c_api.cpp")
+EXAMPLE_BIN = os.path.join(ROOT, "examples", "c_api")
+
+
+def build_example(verbose: bool = False) -> str:
+    """Compile the C ABI example (a host program, no PyTorch) against libspkadd.so."""
+    cmd = [HIPCC, *COMMON_FLAGS, EXAMPLE_SRC, "-L", HERE, "-lspkadd",
+           "-Wl,-rpath,$ORIGIN/../paper_2112_10223_amd", "-o", EXAMPLE_BIN]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"example build failed:\n{res.stderr}")
+    if verbose:
+        print("built", EXAMPLE_BIN)
+    return EXAMPLE_BIN
+
+
 if __name__ == "__main__":
     build_library(verbose=True)
+    build_example(verbose=True)

@@ -261,7 +261,7 @@ spkadd_status spkadd_batch_create(spkadd_batch_t* out, spkadd_dtype dtype, int32
     b->n_cu = cus;
   // bounds blocks: at most 1024, each a multiple of 256 columns
   const long long steps = (max_columns + 255) / 256;
-  const long long nblk0 = steps < 1024 ? steps : 1024;
+  const long long nblk0 = steps < BATCH_MAX_BOUNDS_BLOCKS ? steps : BATCH_MAX_BOUNDS_BLOCKS;
   const int chunk = (int)(256 * ((steps + nblk0 - 1) / nblk0));
   const int nblk = (int)((max_columns + chunk - 1) / chunk);
   b->blob_bytes = blob_size(max_requests, max_inputs);

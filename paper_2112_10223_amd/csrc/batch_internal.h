@@ -38,6 +38,8 @@ constexpr int BSLOTS = BSLOT_WG + 1;
 constexpr int BATCH_WG_U = 4096;
 constexpr int BATCH_WG_SPAN = 1 << 17;
 constexpr int BATCH_WG_THREADS = 256;
+constexpr int BATCH_SCAN_THREADS = 1024;  // one workgroup per request scans its column counts
+constexpr int BATCH_MAX_BOUNDS_BLOCKS = 1024;
 constexpr int BATCH_CHUNK = 16;  // list entries per wavefront task
 
 // Per-request outcome bits (values of SPKADD_REQ_*).

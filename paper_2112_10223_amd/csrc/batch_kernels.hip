@@ -17,6 +17,7 @@
 #include <climits>
 
 #include "batch_device.h"
+#include "scan_device.h"
 
 namespace spk {
 
@@ -27,12 +28,24 @@ __device__ __forceinline__ int batch_wave_index(int u) {
        : e <= 12 ? 8 : 9;
 }
 
-__device__ __forceinline__ int request_of(const BatchReq* __restrict__ reqs, int nreq, int g) {
-  int lo = 0, hi = nreq - 1;  // last r with col_base(r) <= g
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (reqs[mid].col_base <= g) lo = mid;
-    else hi = mid - 1;
+// The request that global column g belongs to: the last r with col_base(r) <= g.
+// `cbase` holds the requests' col_base in LDS when there are at most BATCH_LDS_REQS
+// requests (a search through global memory waits for one load per step).
+constexpr int BATCH_LDS_REQS = 1024;
+__device__ __forceinline__ int request_of(const BatchReq* __restrict__ reqs, const int* cbase, int nreq, int g) {
+  int lo = 0, hi = nreq - 1;
+  if (nreq <= BATCH_LDS_REQS) {
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (cbase[mid] <= g) lo = mid;
+      else hi = mid - 1;
+    }
+  } else {
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (reqs[mid].col_base <= g) lo = mid;
+      else hi = mid - 1;
+    }
   }
   return lo;
 }
@@ -51,22 +64,45 @@ __global__ __launch_bounds__(256) void k_batch_init(BatchArgs b) {
 __global__ __launch_bounds__(256) void k_batch_bounds(BatchArgs b) {
   __shared__ int cnt[BSLOTS];
   __shared__ int wh[4][BSLOTS];
+  __shared__ int cbase[BATCH_LDS_REQS];
   const int lane = lane_id(), w = threadIdx.x >> 6;
   const int nreq = b.hdr->nreq, total = b.hdr->total_cols;
   if (threadIdx.x < BSLOTS) cnt[threadIdx.x] = 0;
+  if (nreq <= BATCH_LDS_REQS)
+    for (int i = threadIdx.x; i < nreq; i += 256) cbase[i] = b.reqs[i].col_base;
   __syncthreads();
   const int c0 = blockIdx.x * b.chunk;
   for (int step = 0; step < b.chunk; step += 256) {
     const int g = c0 + step + threadIdx.x;
     int slot = -1;
     if (g < total) {
-      const int r = request_of(b.reqs, nreq, g);
+      const int r = request_of(b.reqs, cbase, nreq, g);
       const BatchReq& q = b.reqs[r];
       const int j = g - q.col_base;
+      // 16 inputs per round; the next round's colptr pointers are loaded together with
+      // this round's colptr entries (one memory round trip per round).  Global (not
+      // generic) loads, so each wait covers only the memory counter.
+      constexpr int G = 16;
+      const long long cpt = (long long)q.cp;
+      const int kq = q.k;
       long long u = 0;
-      for (int i = 0; i < q.k; ++i) {
-        const int* c = q.cp[i];
-        u += (long long)(c[j + 1] - c[j]);
+      long long ptr[G];
+#pragma unroll
+      for (int t = 0; t < G; ++t) ptr[t] = gload<long long>(cpt + 8LL * min(t, kq - 1));
+      for (int i0 = 0; i0 < kq; i0 += G) {
+        int s[G], e[G];
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+          s[t] = gload<int>(ptr[t] + 4LL * j);
+          e[t] = gload<int>(ptr[t] + 4LL * (j + 1));
+        }
+        if (i0 + G < kq) {
+#pragma unroll
+          for (int t = 0; t < G; ++t) ptr[t] = gload<long long>(cpt + 8LL * min(i0 + G + t, kq - 1));
+        }
+#pragma unroll
+        for (int t = 0; t < G; ++t)
+          if (i0 + t < kq) u += (long long)(e[t] - s[t]);
       }
       b.req_of[g] = r;
       b.colcnt[g] = 0;
@@ -99,23 +135,38 @@ __global__ __launch_bounds__(256) void k_batch_bounds(BatchArgs b) {
 }
 
 // One block of 1024 threads; wavefront w scans slots w, w + 16, ... over the bounds
-// blocks that hold columns of this run (the others find no columns).
+// blocks that hold columns of this run (the others find no columns).  Lane l of a
+// wavefront takes a contiguous run of at most 16 blocks (there are at most
+// BATCH_MAX_BOUNDS_BLOCKS = 1024), all its loads issued together.
 __global__ __launch_bounds__(1024) void k_batch_slot_scan(BatchArgs b) {
+  constexpr int MAXPER = BATCH_MAX_BOUNDS_BLOCKS / 64;
   __shared__ int tot[BSLOTS];
   const int lane = lane_id();
   const int total = b.hdr->total_cols;
   const int used = total > 0 ? (int)(((long long)total + b.chunk - 1) / b.chunk) : 0;
   const int nb = used < b.nblk ? used : b.nblk;
+  const int per = (nb + 63) >> 6, b0 = lane * per;
+  const int last = nb > 0 ? nb - 1 : 0;  // nblk >= 1: row 0 of hist always exists
   for (int s = threadIdx.x >> 6; s < BSLOTS; s += 16) {
-    int carry = 0;
-    for (int base = 0; base < nb; base += 64) {
-      const int t = base + lane;
-      const int v = t < nb ? b.hist[t * BSLOTS + s] : 0;
-      const int incl = wave_scan_add(v);
-      if (t < nb) b.hist[t * BSLOTS + s] = carry + incl - v;
-      carry += readlane(incl, 63);
+    int v[MAXPER];
+    int sum = 0;
+#pragma unroll
+    for (int i = 0; i < MAXPER; ++i) {
+      const int t = b0 + i;
+      const bool mine = i < per && t < nb;
+      const int x = b.hist[min(t, last) * BSLOTS + s];  // clamped index, no guard on the load
+      v[i] = mine ? x : 0;
+      sum += v[i];
     }
-    if (lane == 0) tot[s] = carry;
+    const int incl = wave_scan_add(sum);
+    int run = incl - sum;
+#pragma unroll
+    for (int i = 0; i < MAXPER; ++i) {
+      const int t = b0 + i;
+      if (i < per && t < nb) b.hist[t * BSLOTS + s] = run;
+      run += v[i];
+    }
+    if (lane == 0) tot[s] = readlane(incl, 63);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -171,8 +222,9 @@ __global__ __launch_bounds__(64 * PIPE_WAVES_PER_BLOCK) void k_batch_wave(BatchA
 }
 
 // One workgroup per request: colptr(B_r) by an exclusive scan of its column counts.
-__global__ __launch_bounds__(256) void k_batch_scan(BatchArgs b) {
-  __shared__ long long scratch[256 / 64 + 1];
+__global__ __launch_bounds__(BATCH_SCAN_THREADS) void k_batch_scan(BatchArgs b) {
+  __shared__ long long scratch[BATCH_SCAN_THREADS / 64 + 1];
+  __shared__ int buf[BATCH_SCAN_THREADS * 16];
   const int r = blockIdx.x;
   if (r >= b.hdr->nreq) return;
   const BatchReq& q = b.reqs[r];
@@ -180,27 +232,8 @@ __global__ __launch_bounds__(256) void k_batch_scan(BatchArgs b) {
     if (threadIdx.x == 0) b.nnz[r] = -1;
     return;
   }
-  const int* cnt = b.colcnt + q.col_base;
-  long long carry = 0;
-  constexpr int PER = 8;
-  for (int tile = 0; tile < q.n; tile += 256 * PER) {
-    const int base = tile + threadIdx.x * PER;
-    int v[PER];
-    long long s = 0;
-#pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      v[t] = base + t < q.n ? cnt[base + t] : 0;
-      s += v[t];
-    }
-    long long chunk = 0;
-    long long run = carry + block_excl_scan<256>(s, scratch, &chunk);
-#pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      if (base + t < q.n && run <= INT_MAX) q.colptr_c[base + t] = (int)run;
-      run += v[t];
-    }
-    carry += chunk;
-  }
+  const long long carry = block_scan_counts<BATCH_SCAN_THREADS, 16>(b.colcnt + q.col_base, q.n, q.colptr_c, scratch,
+                                                                      buf);
   if (threadIdx.x == 0) {
     if (carry <= INT_MAX) q.colptr_c[q.n] = (int)carry;
     b.nnz[r] = carry;
@@ -216,7 +249,9 @@ void launch_batch_plan(const BatchArgs& b, hipStream_t s) {
   k_batch_scatter<<<b.nblk, 256, 0, s>>>(b);
 }
 
-void launch_batch_scan(const BatchArgs& b, hipStream_t s) { k_batch_scan<<<b.max_reqs, 256, 0, s>>>(b); }
+void launch_batch_scan(const BatchArgs& b, hipStream_t s) {
+  k_batch_scan<<<b.max_reqs, BATCH_SCAN_THREADS, 0, s>>>(b);
+}
 
 template <bool NUM, typename V, bool BM>
 static void launch_bw(int wi, const BatchArgs& b, const KArgs& a, unsigned blocks, size_t lds, hipStream_t s) {

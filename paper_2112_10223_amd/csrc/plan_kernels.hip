@@ -4,6 +4,7 @@
 
 #include "device.h"
 #include "internal.h"
+#include "scan_device.h"
 
 namespace spk {
 
@@ -480,10 +481,13 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const int* __restr
                                                               long long* __restrict__ bsum) {
   __shared__ long long scratch[SCAN_THREADS / 64 + 1];
   const long long base = (long long)blockIdx.x * SCAN_TILE;
+  const int tlen = (int)(len - base < SCAN_TILE ? len - base : SCAN_TILE);  // >= 1
   long long s = 0;
+#pragma unroll
   for (int t = 0; t < SCAN_PER_THREAD; ++t) {
-    const long long x = base + (long long)t * SCAN_THREADS + threadIdx.x;
-    if (x < len) s += in[x];
+    const int x = t * SCAN_THREADS + (int)threadIdx.x;
+    const int v = in[base + min(x, tlen - 1)];  // clamped index: no guard on the load
+    s += x < tlen ? v : 0;
   }
   s = block_sum<SCAN_THREADS>(s, scratch);
   if (threadIdx.x == 0) bsum[blockIdx.x] = s;
@@ -532,25 +536,57 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const int* __restri
     }
     return;
   }
-  const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_PER_THREAD;
+  // the tile through LDS: coalesced loads and stores, SCAN_PER_THREAD consecutive
+  // entries scanned per thread
+  __shared__ int buf[SCAN_TILE];
+  const long long tile = (long long)blockIdx.x * SCAN_TILE;
+  const int tlen = (int)(len - tile < SCAN_TILE ? len - tile : SCAN_TILE);
+  if (tlen <= 0) return;  // (uniform; the launcher sends only len > SCAN_SMALL here)
+#pragma unroll
+  for (int q = 0; q < SCAN_PER_THREAD; ++q) {
+    const int x = q * SCAN_THREADS + (int)threadIdx.x;
+    const int v = in[tile + min(x, tlen - 1)];  // clamped index: no guard on the load
+    buf[x] = x < tlen ? v : 0;
+  }
+  __syncthreads();
   int v[SCAN_PER_THREAD];
   long long s = 0;
 #pragma unroll
   for (int t = 0; t < SCAN_PER_THREAD; ++t) {
-    const long long x = base + t;
-    v[t] = x < len ? in[x] : 0;
+    v[t] = buf[threadIdx.x * SCAN_PER_THREAD + t];
     s += v[t];
   }
   long long run = pre + block_excl_scan<SCAN_THREADS>(s, scratch);
 #pragma unroll
   for (int t = 0; t < SCAN_PER_THREAD; ++t) {
-    const long long x = base + t;
-    if (x < len) out[x] = (int)run;
+    buf[threadIdx.x * SCAN_PER_THREAD + t] = (int)run;
     run += v[t];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < SCAN_PER_THREAD; ++q) {
+    const int x = q * SCAN_THREADS + (int)threadIdx.x;
+    if (x < tlen) out[tile + x] = buf[x];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     out[len] = (int)all;
     *total = all;
+  }
+}
+
+// Short inputs (len <= SCAN_SMALL): the whole scan in one workgroup, one launch.
+constexpr int SCAN_SMALL_THREADS = 1024, SCAN_SMALL_PER = 16;
+constexpr long long SCAN_SMALL = SCAN_SMALL_THREADS * SCAN_SMALL_PER;  // one tile, 16384
+__global__ __launch_bounds__(SCAN_SMALL_THREADS) void k_scan_small(const int* __restrict__ in, int len,
+                                                                   long long* __restrict__ total,
+                                                                   int* __restrict__ out, int* __restrict__ err) {
+  __shared__ long long scratch[SCAN_SMALL_THREADS / 64 + 1];
+  __shared__ int buf[SCAN_SMALL_THREADS * SCAN_SMALL_PER];
+  const long long all = block_scan_counts<SCAN_SMALL_THREADS, SCAN_SMALL_PER>(in, len, out, scratch, buf);
+  if (threadIdx.x == 0) {
+    *total = all;
+    if (all > INT_MAX) atomicOr(err, ERR_OVERFLOW);
+    else out[len] = (int)all;
   }
 }
 
@@ -654,6 +690,10 @@ size_t scan_tmp_bytes(int64_t len) {
 
 void launch_scan(const int* d_in, int64_t len, int* d_out, long long* d_total, int* d_err, void* d_tmp,
                  hipStream_t s) {
+  if (len <= SCAN_SMALL) {
+    k_scan_small<<<1, SCAN_SMALL_THREADS, 0, s>>>(d_in, (int)len, d_total, d_out, d_err);
+    return;
+  }
   const int nb = (int)((len + SCAN_TILE - 1) / SCAN_TILE);
   long long* bsum = (long long*)d_tmp;
   if (nb > 0) k_scan_reduce<<<nb, SCAN_THREADS, 0, s>>>(d_in, len, bsum);

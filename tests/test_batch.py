@@ -229,6 +229,41 @@ def test_batch_workgroup_columns(values):
     bt.close()
 
 
+def test_batch_long_requests_and_many_bounds_blocks():
+    """Requests of up to 70 001 columns (their colptr scans run several tiles and a
+    ragged tail); a 300 000-column batch spreads the bounds pass over hundreds of
+    blocks."""
+    from paper_2112_10223_amd import binding
+    note("batch long requests")
+    batches = [workloads.er(200, 70001, 3, 0.7, seed=61, values="int32f"),
+               workloads.er(5000, 16385, 4, 2.0, seed=62, values="int32f"),
+               workloads.er(50, 1, 2, 3.0, seed=63, values="int32f"),
+               workloads.er(3000, 40000, 2, 1.5, seed=64, values="int32f")]
+    bt = _batch(binding.SPKADD_F32, 8, 300000, 64)
+    for use_graph in (False, True):
+        reqs = _requests(batches)
+        bt.run(reqs, use_graph=use_graph)
+        nnz, st = bt.results()
+        _check_all(batches, reqs, nnz, st, exact=True)
+    bt.close()
+
+
+def test_batch_many_requests():
+    """More requests than the kernels keep in on-chip memory (1024): the column to
+    request search then reads the request table in device memory."""
+    from paper_2112_10223_amd import binding
+    note("batch many requests")
+    rng = np.random.default_rng(71)
+    batches = [workloads.er(int(rng.integers(1, 300)), int(rng.integers(0, 5)), int(rng.integers(1, 4)),
+                            float(rng.uniform(0, 4)), seed=7100 + t, values="int32f") for t in range(1100)]
+    bt = _batch(binding.SPKADD_F32, 1100, 5000, 3300)
+    reqs = _requests(batches)
+    bt.run(reqs, use_graph=True)
+    nnz, st = bt.results()
+    _check_all(batches, reqs, nnz, st, exact=True)
+    bt.close()
+
+
 def test_batch_equals_plain_path():
     """The batched and the one-request launches give identical bits on the same
     requests (integer-valued inputs: every order of summation is exact)."""

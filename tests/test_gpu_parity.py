@@ -310,6 +310,15 @@ def test_edge_shapes():
     plan.free()
 
 
+@pytest.mark.parametrize("n", [16383, 16384, 65536, 100003, 131072, 131073, 200000])
+def test_scan_lengths(n):
+    """colptr(B) over column counts of every length around the scan's tile and path
+    limits (one workgroup up to 2^17 columns, tile sums beyond)."""
+    note(f"scan_lengths n={n}")
+    b = workloads.er(40, n, 2, 0.6, seed=n % 9973, values="int32f")
+    assert_matches(b, run_gpu(b), oracle.spkadd(b), exact_values=True)
+
+
 def test_same_row_everywhere_and_large_k():
     note("same_row_everywhere_and_large_k")
     k, m, n = 200, 1000, 40
