@@ -157,7 +157,8 @@ int enqueue_wg(spkadd_batch_s* b, bool numeric, hipStream_t s) {
   a.err = b->args.err;
   a.dummy = b->args.dummy;
   a.alpha_q = 512;
-  lds_layout_bitmap_wg(numeric, f64 ? 8 : 4, 64, BATCH_WG_SPAN, BATCH_WG_U, a);
+  // every workgroup-slot column has at most BATCH_WG_U entries, all in registers
+  lds_layout_bitmap_wg(numeric, f64 ? 8 : 4, 64, BATCH_WG_SPAN, BATCH_WG_U, BATCH_WG_U, true, 2, a);
   int bpc = max_lds_bytes() / a.slice_bytes;
   bpc = bpc < 1 ? 1 : bpc > 8 ? 8 : bpc;
   launch_batch_wg(numeric, f64, b->args, a, (unsigned)(b->n_cu * bpc), s);

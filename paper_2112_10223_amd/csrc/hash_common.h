@@ -66,7 +66,12 @@ __device__ __forceinline__ int build_meta(const KArgs& a, int j, bool win, int b
   for (int base = 0; base < a.k; base += 64) {
     const int i = base + lane;
     int s = 0, e = 0;
+    const int* rp = nullptr;
+    const V* vp = nullptr;
     if (i < a.k) {
+      // the row / value pointers are fetched together with the segment bounds
+      rp = a.ri[i];
+      if (NUM) vp = (const V*)a.va[i];
       if (win) {
         s = a.bpos[(long long)blo * a.k + i];
         e = max(a.bpos[(long long)(blo + 1) * a.k + i], s);  // (only an unsorted input could invert them)
@@ -81,8 +86,8 @@ __device__ __forceinline__ int build_meta(const KArgs& a, int j, bool win, int b
     const int ex = carry + incl - len;
     if (i < a.k) {
       P[i] = ex;
-      adj[i] = (long long)(a.ri[i] + s) - 4LL * ex;
-      if (NUM) adjv[i] = (long long)((const V*)a.va[i] + s) - (long long)sizeof(V) * ex;
+      adj[i] = (long long)(rp + s) - 4LL * ex;
+      if (NUM) adjv[i] = (long long)(vp + s) - (long long)sizeof(V) * ex;
     }
     carry += wave_bcast(incl, 63);
   }

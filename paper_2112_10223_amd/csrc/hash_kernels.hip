@@ -203,11 +203,11 @@ __global__ __launch_bounds__(NT) void k_hash_wg(KArgs a, const int* __restrict__
   const int tid = threadIdx.x;
   int j, blo = 0, rlo = 0, rhi = a.m;
   if (WIN) {
-    const int c = a.win_c[unit];
-    j = a.wcols[c];
-    blo = unit + c;
-    rlo = a.brow[blo];
-    rhi = a.brow[blo + 1];
+    const int4 w = a.wrec[unit];
+    j = w.x;
+    rlo = w.y;
+    rhi = w.z;
+    blo = w.w;
   } else {
     j = list[unit];
   }

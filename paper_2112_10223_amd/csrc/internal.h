@@ -82,6 +82,7 @@ struct KArgs {
   const int* wcols;       // window column list (column ids)
   const int* win_c;       // window -> index into wcols
   const int* brow;        // boundary rows; window w spans boundaries w + win_c[w] and the next
+  const int4* wrec;       // per window: column id, first row, end row, lower boundary index
   const int* bpos;        // boundary positions, k per boundary
   const int* cntin;       // window input entry counts
   int* win_cnt;           // symbolic: per-window unique rows
@@ -97,6 +98,8 @@ struct KArgs {
   // workgroup units: units at most wg_span_max rows wide go to the bitmap kernel (the
   // hash kernel skips them); wg_cap = its staging capacity in output entries
   int wg_span_max, wg_cap;
+  int wg_overlay;         // the staging area may overlay the bitmap (ranks read first)
+  int wg_group;           // bitmap words per prefix entry (2 or 4)
   int unsorted;           // numeric: 1 = write each column in table order (no sort)
 };
 
@@ -125,6 +128,8 @@ void launch_win_fill(const PlanParams& p, int n_wcols, const int* d_wfirst, int*
 void launch_win_search(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
                        const int* d_wfirst, const int* d_u, int n_wcols, int n_bounds, const int* d_bcol,
                        const int* d_brow, int* d_bpos, hipStream_t s);
+void launch_win_records(int n_windows, const int* d_wcols, const int* d_win_c, const int* d_brow, int4* d_wrec,
+                        hipStream_t s);
 void launch_win_count(const PlanParams& p, int n_windows, const int* d_win_c, const int* d_brow, const int* d_bpos,
                       int* d_cntin, int* d_q, PlanSummary* d_sum, hipStream_t s);
 void launch_win_refine_fill(int n_windows, int n_wcols, const int* d_win_c, const int* d_wfirst_old,
@@ -163,7 +168,11 @@ void lds_layout_pipe(int bin, bool numeric, int vbytes, int ts_max, int bm_nq, K
 // Workgroup bitmap kernel (bitmap_wg.hip): widest unit it takes (rows), LDS layout,
 // launch over a bin's units (G1, G2 or WIN).
 int bitmap_wg_span_max();
-void lds_layout_bitmap_wg(bool numeric, int vbytes, int k, int span_max, int cap, KArgs& a);
+// one_max: a unit with at most this many entries keeps them all in registers (the
+// launch's threads x entries per thread); all_one: every unit of the launch does.
+void lds_layout_bitmap_wg(bool numeric, int vbytes, int k, int span_max, int cap, int one_max, bool all_one, int G,
+                          KArgs& a);
+int bitmap_wg_regs(int bin);
 hipError_t launch_bitmap_wg(int bin, bool numeric, bool f64, const KArgs& a, const int* d_list, int nunits,
                             hipStream_t s);
 hipError_t launch_wave_pipe(int bin, bool numeric, bool f64, const KArgs& a, const int* d_list, int nunits,

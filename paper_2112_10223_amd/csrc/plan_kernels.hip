@@ -451,6 +451,18 @@ __global__ __launch_bounds__(256) void k_win_refine_search(PlanParams p, const i
   bpos_new[t] = pos;
 }
 
+// The final windows as one record each (column id, rows [rlo, rhi), lower boundary):
+// a window kernel then starts from one load instead of a chain of three.
+__global__ __launch_bounds__(256) void k_win_records(int n_windows, const int* __restrict__ wcols,
+                                                     const int* __restrict__ win_c, const int* __restrict__ brow,
+                                                     int4* __restrict__ wrec) {
+  const int w = blockIdx.x * 256 + threadIdx.x;
+  if (w >= n_windows) return;
+  const int c = win_c[w];
+  const int b = w + c;
+  wrec[w] = make_int4(wcols[c], brow[b], brow[b + 1], b);
+}
+
 // Per window column: nnz(B(:,j)) = sum of its window counts, and each window's
 // offset inside the column.
 __global__ __launch_bounds__(256) void k_win_colsum(int n_wcols, const int* __restrict__ wcols,
@@ -675,6 +687,12 @@ void launch_win_refine_search(const PlanParams& p, const int* const* d_ri, int n
   if (work == 0) return;
   k_win_refine_search<<<grid_for(work, 256), 256, 0, s>>>(p, d_ri, n_bounds_new, d_bcol_new, d_brow_new, d_bpar,
                                                           d_bpiece, d_q, d_bpos_old, d_bpos_new);
+}
+
+void launch_win_records(int n_windows, const int* d_wcols, const int* d_win_c, const int* d_brow, int4* d_wrec,
+                        hipStream_t s) {
+  if (n_windows <= 0) return;
+  k_win_records<<<grid_for(n_windows, 256), 256, 0, s>>>(n_windows, d_wcols, d_win_c, d_brow, d_wrec);
 }
 
 void launch_win_colsum(int n_wcols, const int* d_wcols, const int* d_wfirst, const int* d_win_cnt, int* d_colcnt,

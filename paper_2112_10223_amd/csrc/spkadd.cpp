@@ -267,6 +267,7 @@ struct spkadd_plan_s {
   int* d_cntin = nullptr;
   int* d_win_cnt = nullptr;
   int* d_win_off = nullptr;
+  int4* d_wrec = nullptr;
   int n_cu = 256;
   void* d_dummy = nullptr;
   // scan
@@ -400,6 +401,7 @@ KArgs base_args(const spkadd_plan_s* p) {
   a.wcols = p->d_list + p->binoff[BIN_WIN];
   a.win_c = p->d_win_c;
   a.brow = p->d_brow;
+  a.wrec = p->d_wrec;
   a.bpos = p->d_bpos;
   a.cntin = p->d_cntin;
   a.win_cnt = p->d_win_cnt;
@@ -558,6 +560,12 @@ spkadd_status build_windows(spkadd_plan_s* p, hipStream_t s) {
   p->max_span = p->h_sum->max_span;  // of the last level counted (the final windows)
   if ((st = p->alloc(&p->d_win_cnt, W, s))) return st;
   if ((st = p->alloc(&p->d_win_off, W, s))) return st;
+  if ((st = p->alloc(&p->d_wrec, W, s))) return st;
+  {
+    TraceScope t(p, "win_records", s);
+    launch_win_records(W, wcols, p->d_win_c, p->d_brow, p->d_wrec, s);
+  }
+  HIP_TRY(hipGetLastError());
   return SPKADD_OK;
 }
 
@@ -603,7 +611,19 @@ void wg_bitmap_layout(const spkadd_plan_s* p, int b, bool numeric, KArgs& a, boo
   const long long need = worst ? cap : b == BIN_WIN ? p->max_span : p->m;
   int span = 1024;
   while (span < need && span < cap) span <<= 1;
-  lds_layout_bitmap_wg(numeric, p->dtype == SPKADD_F64 ? 8 : 4, p->k, span, p->pp.cap_in, a);
+  const int vb = p->dtype == SPKADD_F64 ? 8 : 4, regs = bitmap_wg_regs(b);
+  lds_layout_bitmap_wg(numeric, vb, p->k, span, p->pp.cap_in, regs, false, 2, a);
+  if (!numeric) return;
+  // groups of four words halve the prefix; worth their costlier ranks only where that
+  // lets another workgroup reside (resident waves per CU are capped at 32)
+  KArgs a4 = a;
+  lds_layout_bitmap_wg(numeric, vb, p->k, span, p->pp.cap_in, regs, false, 4, a4);
+  const int waves = (b == BIN_G1 ? G1_THREADS : G2_THREADS) / 64, lmax = max_lds_bytes();
+  auto resident = [&](const KArgs& x) {
+    const int by_lds = lmax / (x.slice_bytes > 0 ? x.slice_bytes : 1), by_waves = 32 / waves;
+    return by_lds < by_waves ? by_lds : by_waves;
+  };
+  if (resident(a4) > resident(a)) a = a4;
 }
 
 // Launches the symbolic or numeric kernel of bin b.
@@ -621,6 +641,7 @@ hipError_t launch_bin(spkadd_plan_s* p, int b, bool numeric, KArgs& a, hipStream
     if (e != hipSuccess || b != BIN_WIN || p->max_span <= ab.wg_span_max) return e;
     layout_bin(p, b, numeric, a);
     a.wg_span_max = ab.wg_span_max;
+    TraceScope t(p, numeric ? "num_window_wide" : "sym_window_wide", s, numeric);
     return launch_hash(b, numeric, f64, a, list, cnt, s);
   }
   if (layout_bin(p, b, numeric, a)) {
