@@ -375,6 +375,21 @@ def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 5) -> float:
     return round(2 * nbytes / (best * 1e-3) / 1e9, 1)
 
 
+def reversed_columns(batch):
+    """The same matrices with every column's entries in descending row order."""
+    import workloads
+    rows, vals = [], []
+    for i in range(batch.k):
+        cp = batch.colptr[i].astype(np.int64)
+        lens = np.diff(cp)
+        # entry p of column j moves to cp[j] + cp[j+1] - 1 - p
+        ends = np.repeat(cp[:-1] + cp[1:] - 1, lens)
+        src = ends - np.arange(cp[-1], dtype=np.int64)
+        rows.append(np.ascontiguousarray(batch.rowidx[i][src]))
+        vals.append(np.ascontiguousarray(batch.vals[i][src]))
+    return workloads.CSCBatch(batch.m, batch.n, batch.colptr, rows, vals)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -386,6 +401,8 @@ def main() -> int:
     ap.add_argument("--no-trace", action="store_true", help="time without per-kernel events")
     ap.add_argument("--trace-steps", type=int, default=3, help="untimed steps with every launch traced")
     ap.add_argument("--tune", action="store_true", help="autotune the launch parameters on the workload first")
+    ap.add_argument("--unsorted-in", action="store_true",
+                    help="every input column reversed (descending rows), planned with SPKADD_FLAG_UNSORTED_IN")
     ap.add_argument("--unsorted-out", action="store_true",
                     help="rows of each output column in any order (hash accumulators skip their sort)")
     ap.add_argument("--batched", type=int, default=400,
@@ -407,6 +424,8 @@ def main() -> int:
 
     desc, make = WORKLOADS[args.workload]
     batch = make()
+    if args.unsorted_in:
+        batch = reversed_columns(batch)
     k, m, n = batch.k, batch.m, batch.n
     f64 = batch.vals[0].dtype == np.float64
     vbytes = 8 if f64 else 4
@@ -417,7 +436,8 @@ def main() -> int:
     dtype = binding.SPKADD_F64 if f64 else binding.SPKADD_F32
     # timed steps record HIP events around the numeric launches only (the dominant
     # kernels); a separate untimed pass traces every launch for the phase breakdown
-    order = binding.SPKADD_FLAG_UNSORTED_OUT if args.unsorted_out else 0
+    order = (binding.SPKADD_FLAG_UNSORTED_OUT if args.unsorted_out else 0) | \
+        (binding.SPKADD_FLAG_UNSORTED_IN if args.unsorted_in else 0)
     opts = binding.make_opts(flags=order | (0 if args.no_trace else binding.SPKADD_FLAG_TRACE_NUMERIC))
     opts_all = binding.make_opts(flags=order | binding.SPKADD_FLAG_TRACE)
     tuned = None
@@ -571,7 +591,8 @@ def main() -> int:
         "data": "synthetic (seeded generator; paper's R-MAT family, no public datasets)",
         "config": {"workload": f"{args.workload}: {desc}", "k": k, "m": m, "n": n, "nnz_in": nnz_in,
                    "nnz_out": nnz_out, "parallelism": "single GPU",
-                   "output_order": "any" if args.unsorted_out else "sorted"},
+                   "output_order": "any" if args.unsorted_out else "sorted",
+                   "input_order": "descending (reversed columns)" if args.unsorted_in else "ascending"},
         "hbm_gbps_alg_step": round(b_alg / (ms_per_step * 1e-3) / 1e9, 1),
         "hbm_frac_alg_step": round(b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "hbm_gbps_min_step": round(b_min / (ms_per_step * 1e-3) / 1e9, 1),

@@ -15,7 +15,8 @@
  *
  * Formats (Section II-A, CSC storage).  Every matrix is CSC with
  *   colptr : int32[n+1], colptr[0] = 0, non-decreasing;
- *   rowidx : int32[nnz], rows in [0, m), strictly ascending within each column;
+ *   rowidx : int32[nnz], rows in [0, m), strictly ascending within each column (in any
+ *            order under SPKADD_FLAG_UNSORTED_IN);
  *   values : float[nnz] (SPKADD_F32) or double[nnz] (SPKADD_F64).
  * The output B is canonical CSC in the same form.  Its pattern is the union of
  * the input patterns: explicit zeros and cancellations stay stored, because the
@@ -67,6 +68,13 @@ typedef enum spkadd_dtype { SPKADD_F32 = 0, SPKADD_F64 = 1 } spkadd_dtype;
 #define SPKADD_FLAG_UNSORTED_OUT 8u  /* the rows of each output column may come in any order: the hash
                                         accumulators skip their sort (the paper's "if sorted output is
                                         desired", Algorithm 5); bitmap accumulators are sorted anyway */
+#define SPKADD_FLAG_UNSORTED_IN 16u  /* the rows of each input column may come in any order (hash
+                                        accumulation needs none, Table I).  The row windows of long
+                                        columns then count their entries by histogram and partition
+                                        them into one bucket per window in spkadd_plan (about 16 bytes
+                                        of device memory per such entry, plus 4 or 8 gathered in
+                                        each spkadd_numeric) instead of binary-searching sorted
+                                        columns.  Duplicate rows within a column are still summed. */
 
 /* opts.force_bin: test hook that routes columns to one accumulator family */
 #define SPKADD_BIN_AUTO (-1)

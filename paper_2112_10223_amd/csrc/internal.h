@@ -51,6 +51,7 @@ struct PlanParams {
   int cap_in;       // largest input count of a G2 column or a window
   int force_bin;    // -1 auto
   float win_fill;   // target window input count = cap_in * win_fill
+  int unsorted_in;  // input columns may be unsorted (validation checks only the row range)
 };
 
 // Summary written by the plan kernels; the host reads it from a pinned slot.
@@ -130,6 +131,18 @@ void launch_win_search(const PlanParams& p, const int* const* d_cp, const int* c
                        const int* d_brow, int* d_bpos, hipStream_t s);
 void launch_win_records(int n_windows, const int* d_wcols, const int* d_win_c, const int* d_brow, int4* d_wrec,
                         hipStream_t s);
+// Unsorted input (unsorted_kernels.hip): window counts by histogram, the bucket
+// partition of the final windows, and the numeric pass's value gather.
+void launch_uwin_hist(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int n_wcols,
+                      const int* d_wcols, const int* d_wfirst, const int* d_brow, int* d_cnt, hipStream_t s);
+void launch_uwin_scatter(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int n_wcols,
+                         const int* d_wcols, const int* d_wfirst, const int* d_brow, const int* d_boff, int* d_gcur,
+                         int* d_brows, long long* d_bsrc, hipStream_t s);
+void launch_uwin_bpos(int n_windows, const int* d_win_c, const int* d_wfirst, const int* d_boff, int* d_bpos,
+                      hipStream_t s);
+void launch_uwin_gather(long long total, const long long* d_bsrc, const void* const* d_va, void* d_bvals, bool f64,
+                        hipStream_t s);
+// d_bpos NULL: the counts are already in d_cntin (unsorted input)
 void launch_win_count(const PlanParams& p, int n_windows, const int* d_win_c, const int* d_brow, const int* d_bpos,
                       int* d_cntin, int* d_q, PlanSummary* d_sum, hipStream_t s);
 void launch_win_refine_fill(int n_windows, int n_wcols, const int* d_win_c, const int* d_wfirst_old,

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_bounds(PlanParams p, const int
 }
 
 // Optional input validation: colptr_i[0] = 0, colptr non-decreasing, rows in [0, m)
-// and strictly ascending within every column.
+// and (unless the input is declared unsorted) strictly ascending within every column.
 __global__ __launch_bounds__(PLAN_THREADS) void k_validate(PlanParams p, const int* const* __restrict__ cp,
                                                            const int* const* __restrict__ ri,
                                                            PlanSummary* __restrict__ sum) {
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_validate(PlanParams p, const i
     int prev = -1;
     for (int q = s; q < e; ++q) {
       const int row = r[q];
-      if (row <= prev || row >= p.m) bad = true;
+      if ((!p.unsorted_in && row <= prev) || row < 0 || row >= p.m) bad = true;
       prev = row;
     }
   }
@@ -377,10 +377,14 @@ __global__ __launch_bounds__(256) void k_win_count(PlanParams p, int n_windows, 
   const int w = blockIdx.x * 256 + threadIdx.x;
   if (w >= n_windows) return;
   const int b = w + win_c[w];
-  const int* lo = bpos + (long long)b * p.k;
-  const int* hi = lo + p.k;
   long long cnt = 0;
-  for (int i = 0; i < p.k; ++i) cnt += max(hi[i] - lo[i], 0);  // (inverted only for an unsorted input)
+  if (bpos) {
+    const int* lo = bpos + (long long)b * p.k;
+    const int* hi = lo + p.k;
+    for (int i = 0; i < p.k; ++i) cnt += max(hi[i] - lo[i], 0);  // (inverted only for an unsorted input)
+  } else {
+    cnt = cntin[w];  // counted by histogram (unsorted input)
+  }
   const int width = brow[b + 1] - brow[b];
   atomicMax(&sum->max_span, width);
   int pieces = 1;

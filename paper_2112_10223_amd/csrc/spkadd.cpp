@@ -268,6 +268,14 @@ struct spkadd_plan_s {
   int* d_win_cnt = nullptr;
   int* d_win_off = nullptr;
   int4* d_wrec = nullptr;
+  // unsorted input: the window columns' entries in one bucket per window
+  bool unsorted_in = false;
+  long long u_total = 0;           // entries in the buckets
+  int* d_ubrows = nullptr;         // bucket rows
+  long long* d_ubsrc = nullptr;    // (input << 32 | position) of each bucket entry
+  void* d_ubvals = nullptr;        // bucket values, gathered by each numeric pass
+  int* d_ubpos = nullptr;          // bucket boundaries, in the one-input layout of bpos
+  const void** d_utab = nullptr;   // [0]: bucket rows, [1]: bucket values (one-input pointer tables)
   int n_cu = 256;
   void* d_dummy = nullptr;
   // scan
@@ -570,6 +578,119 @@ spkadd_status build_windows(spkadd_plan_s* p, hipStream_t s) {
 }
 
 
+// Row windows of unsorted input columns: the same splits as build_windows, with each
+// level's window counts from a histogram of the column's rows against its window
+// boundaries (no binary search, which needs sorted columns); the final windows' entries
+// are then partitioned into one bucket per window.
+spkadd_status build_windows_unsorted(spkadd_plan_s* p, hipStream_t s) {
+  spkadd_status st;
+  const int nwc = p->n_wcols;
+  int W = p->n_windows;
+  if ((st = p->alloc(&p->d_win_c, W, s))) return st;
+  if ((st = p->alloc(&p->d_brow, (size_t)W + nwc, s))) return st;
+  if ((st = p->alloc(&p->d_bcol, (size_t)W + nwc, s))) return st;
+  if ((st = p->alloc(&p->d_cntin, W, s))) return st;
+  int* d_q = nullptr;
+  if ((st = p->alloc(&d_q, W, s))) return st;
+  const int* wcols = p->d_list + p->binoff[BIN_WIN];
+  {
+    TraceScope t(p, "win_fill", s);
+    launch_win_fill(p->pp, nwc, p->d_wfirst, p->d_win_c, p->d_brow, p->d_bcol, s);
+  }
+  p->levels = 0;
+  for (;;) {
+    HIP_TRY(hipMemsetAsync(p->d_cntin, 0, (size_t)W * sizeof(int), s));
+    {
+      TraceScope t(p, "uwin_hist", s);
+      launch_uwin_hist(p->pp, p->d_cp, p->d_ri, nwc, wcols, p->d_wfirst, p->d_brow, p->d_cntin, s);
+    }
+    HIP_TRY(hipMemsetAsync(&p->d_sum->pad, 0, 2 * sizeof(int), s));  // pad and max_span
+    {
+      TraceScope t(p, "win_count", s);
+      launch_win_count(p->pp, W, p->d_win_c, p->d_brow, nullptr, p->d_cntin, d_q, p->d_sum, s);
+    }
+    HIP_TRY(hipGetLastError());
+    if ((st = sync_summary(p, s))) return st;
+    if (p->h_sum->pad == 0) break;
+    if (++p->levels > 64) return set_error(SPKADD_ERR_HIP, "window refinement did not converge");
+    int* d_newfirst = nullptr;
+    void* tmp = nullptr;
+    if ((st = p->alloc(&d_newfirst, (size_t)W + 1, s))) return st;
+    if ((st = p->alloc((char**)&tmp, scan_tmp_bytes(W), s))) return st;
+    launch_scan(d_q, W, d_newfirst, &p->d_sum->total, &p->d_sum->err, tmp, s);
+    if ((st = sync_summary(p, s))) return st;
+    const long long total = p->h_sum->total;
+    if (total > INT_MAX / 2) return set_error(SPKADD_ERR_OVERFLOW, "too many row windows (%lld)", total);
+    const int W2 = (int)total;
+    int *win_c2, *brow2, *bcol2, *bpar, *bpiece, *wfirst2, *cntin2, *q2;
+    if ((st = p->alloc(&win_c2, W2, s))) return st;
+    if ((st = p->alloc(&brow2, (size_t)W2 + nwc, s))) return st;
+    if ((st = p->alloc(&bcol2, (size_t)W2 + nwc, s))) return st;
+    if ((st = p->alloc(&bpar, (size_t)W2 + nwc, s))) return st;
+    if ((st = p->alloc(&bpiece, (size_t)W2 + nwc, s))) return st;
+    if ((st = p->alloc(&wfirst2, (size_t)nwc + 1, s))) return st;
+    if ((st = p->alloc(&cntin2, W2, s))) return st;
+    if ((st = p->alloc(&q2, W2, s))) return st;
+    {
+      TraceScope t(p, "win_refine_fill", s);
+      launch_win_refine_fill(W, nwc, p->d_win_c, p->d_wfirst, d_q, d_newfirst, p->d_brow, win_c2, brow2, bcol2,
+                             bpar, bpiece, wfirst2, s);
+    }
+    for (void* x : {(void*)p->d_win_c, (void*)p->d_brow, (void*)p->d_bcol, (void*)p->d_cntin, (void*)d_q,
+                    (void*)p->d_wfirst, (void*)d_newfirst, tmp, (void*)bpar, (void*)bpiece})
+      p->release(x, s);
+    p->d_win_c = win_c2;
+    p->d_brow = brow2;
+    p->d_bcol = bcol2;
+    p->d_cntin = cntin2;
+    p->d_wfirst = wfirst2;
+    d_q = q2;
+    W = W2;
+  }
+  p->release(d_q, s);
+  p->n_windows = W;
+  p->max_span = p->h_sum->max_span;
+  // buckets: offsets, boundaries in the one-input layout, then the partition
+  int* d_boff = nullptr;
+  int* d_gcur = nullptr;
+  void* tmp = nullptr;
+  if ((st = p->alloc(&d_boff, (size_t)W + 1, s))) return st;
+  if ((st = p->alloc((char**)&tmp, scan_tmp_bytes(W), s))) return st;
+  launch_scan(p->d_cntin, W, d_boff, &p->d_sum->total, &p->d_sum->err, tmp, s);
+  if ((st = sync_summary(p, s))) return st;
+  if ((st = check_device_err(p))) return st;
+  p->u_total = p->h_sum->total;
+  const int vb = p->dtype == SPKADD_F64 ? 8 : 4;
+  if ((st = p->alloc(&p->d_ubpos, (size_t)W + nwc, s))) return st;
+  if ((st = p->alloc(&p->d_ubrows, (size_t)p->u_total, s))) return st;
+  if ((st = p->alloc(&p->d_ubsrc, (size_t)p->u_total, s))) return st;
+  if ((st = p->alloc((char**)&p->d_ubvals, (size_t)p->u_total * vb, s))) return st;
+  if ((st = p->alloc(&p->d_utab, 2, s))) return st;
+  if ((st = p->alloc(&d_gcur, W, s))) return st;
+  launch_uwin_bpos(W, p->d_win_c, p->d_wfirst, d_boff, p->d_ubpos, s);
+  HIP_TRY(hipMemcpyAsync(d_gcur, d_boff, (size_t)W * sizeof(int), hipMemcpyDeviceToDevice, s));
+  {
+    TraceScope t(p, "uwin_scatter", s);
+    launch_uwin_scatter(p->pp, p->d_cp, p->d_ri, nwc, wcols, p->d_wfirst, p->d_brow, d_boff, d_gcur, p->d_ubrows,
+                        p->d_ubsrc, s);
+  }
+  const void* tab[2] = {p->d_ubrows, p->d_ubvals};
+  launch_put_ptrs(tab, 2, p->d_utab, nullptr, nullptr, s);
+  HIP_TRY(hipGetLastError());
+  p->release(tmp, s);
+  p->release(d_boff, s);
+  p->release(d_gcur, s);
+  if ((st = p->alloc(&p->d_win_cnt, W, s))) return st;
+  if ((st = p->alloc(&p->d_win_off, W, s))) return st;
+  if ((st = p->alloc(&p->d_wrec, W, s))) return st;
+  {
+    TraceScope t(p, "win_records", s);
+    launch_win_records(W, wcols, p->d_win_c, p->d_brow, p->d_wrec, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return SPKADD_OK;
+}
+
 bool is_wave(int b) { return b >= BIN_W1 && b <= BIN_W16; }
 
 // Bitmap rows (of 256 words) for a wave bin, or 0 for hash tables.
@@ -627,9 +748,17 @@ void wg_bitmap_layout(const spkadd_plan_s* p, int b, bool numeric, KArgs& a, boo
 }
 
 // Launches the symbolic or numeric kernel of bin b.
-hipError_t launch_bin(spkadd_plan_s* p, int b, bool numeric, KArgs& a, hipStream_t s) {
+hipError_t launch_bin(spkadd_plan_s* p, int b, bool numeric, KArgs& a_in, hipStream_t s) {
   const int cnt = b == BIN_WIN ? p->n_windows : p->bin_count[b];
   if (cnt == 0) return hipSuccess;
+  KArgs a = a_in;
+  if (b == BIN_WIN && p->unsorted_in) {  // the buckets: one input, boundaries in bpos layout
+    a.k = 1;
+    a.ktop = 0;
+    a.ri = (const int* const*)p->d_utab;
+    a.va = (const void* const*)(p->d_utab + 1);
+    a.bpos = p->d_ubpos;
+  }
   const bool f64 = p->dtype == SPKADD_F64;
   const int* list = b == BIN_WIN ? nullptr : p->d_list + p->binoff[b];
   if (wg_bitmap_bin(p, b)) {
@@ -748,6 +877,8 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
   p->pp.g1_max = g1;
   p->pp.force_bin = o.force_bin;
   p->pp.win_fill = o.window_fill > 0 ? o.window_fill : kDefaultFill;
+  p->unsorted_in = (o.flags & SPKADD_FLAG_UNSORTED_IN) != 0;
+  p->pp.unsorted_in = p->unsorted_in ? 1 : 0;
   for (int b = BIN_W1; b <= BIN_W16; ++b) {
     p->ts_sym[b] = table_slots(64 * wave_bin_E(b), p->alpha_sym_q);
     p->ts_num[b] = table_slots(64 * wave_bin_E(b), p->alpha_num_q);
@@ -858,7 +989,7 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
     if ((st = check_device_err(p))) return fail(st);
     p->n_windows = p->h_sum->n_windows;
     if ((st = check_lds(p))) return fail(st);
-    if ((st = build_windows(p, stream))) return fail(st);
+    if ((st = (p->unsorted_in ? build_windows_unsorted(p, stream) : build_windows(p, stream)))) return fail(st);
     if ((st = check_device_err(p))) return fail(st);
   }
   *out = p;
@@ -930,6 +1061,11 @@ spkadd_status spkadd_numeric(spkadd_plan_t p, const void* const* values, int32_t
   a.colptr_c = p->colptr_c;
   a.out_r = rowidx_c;
   a.out_v = values_c;
+  if (p->unsorted_in && p->n_windows > 0) {
+    TraceScope t(p, "uwin_gather", stream, true);
+    launch_uwin_gather(p->u_total, p->d_ubsrc, (const void* const*)p->d_va, p->d_ubvals,
+                       p->dtype == SPKADD_F64, stream);
+  }
   for (int b = BIN_W1; b < NBINS; ++b) {
     const int cnt = b == BIN_WIN ? p->n_windows : p->bin_count[b];
     if (cnt == 0) continue;

@@ -52,3 +52,16 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_reversed_columns(bench):
+    """--unsorted-in input: every column's entries in reverse order, nothing else moved."""
+    import workloads
+    b = workloads.er(50, 7, 3, 4.0, seed=3, values="int32f")
+    r = bench.reversed_columns(b)
+    assert np.array_equal(r.colptr, b.colptr)
+    for i in range(b.k):
+        for j in range(b.n):
+            s, e = b.colptr[i][j], b.colptr[i][j + 1]
+            assert np.array_equal(r.rowidx[i][s:e], b.rowidx[i][s:e][::-1])
+            assert np.array_equal(r.vals[i][s:e], b.vals[i][s:e][::-1])
