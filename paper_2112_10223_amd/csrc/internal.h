@@ -133,11 +133,15 @@ void launch_win_records(int n_windows, const int* d_wcols, const int* d_win_c, c
                         hipStream_t s);
 // Unsorted input (unsorted_kernels.hip): window counts by histogram, the bucket
 // partition of the final windows, and the numeric pass's value gather.
-void launch_uwin_hist(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int n_wcols,
-                      const int* d_wcols, const int* d_wfirst, const int* d_brow, int* d_cnt, hipStream_t s);
-void launch_uwin_scatter(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int n_wcols,
-                         const int* d_wcols, const int* d_wfirst, const int* d_brow, const int* d_boff, int* d_gcur,
-                         int* d_brows, long long* d_bsrc, hipStream_t s);
+void launch_uwin_chunks(const PlanParams& p, int n_wcols, const int* d_wcols, const int* d_u, int* d_nch,
+                        hipStream_t s);
+void launch_uwin_chfill(int n_wcols, const int* d_chfirst, int* d_chcol, hipStream_t s);
+void launch_uwin_hist(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int n_chunks,
+                      const int* d_wcols, const int* d_wfirst, const int* d_brow, const int* d_chfirst,
+                      const int* d_chcol, int* d_cnt, hipStream_t s);
+void launch_uwin_scatter(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int n_chunks,
+                         const int* d_wcols, const int* d_wfirst, const int* d_brow, const int* d_chfirst,
+                         const int* d_chcol, int* d_gcur, int* d_brows, long long* d_bsrc, hipStream_t s);
 void launch_uwin_bpos(int n_windows, const int* d_win_c, const int* d_wfirst, const int* d_boff, int* d_bpos,
                       hipStream_t s);
 void launch_uwin_gather(long long total, const long long* d_bsrc, const void* const* d_va, void* d_bvals, bool f64,

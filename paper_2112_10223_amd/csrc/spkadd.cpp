@@ -597,12 +597,27 @@ spkadd_status build_windows_unsorted(spkadd_plan_s* p, hipStream_t s) {
     TraceScope t(p, "win_fill", s);
     launch_win_fill(p->pp, nwc, p->d_wfirst, p->d_win_c, p->d_brow, p->d_bcol, s);
   }
+  // work units of the passes over the columns' entries: chunks of each column
+  int *d_nch = nullptr, *d_chfirst = nullptr, *d_chcol = nullptr;
+  void* chtmp = nullptr;
+  if ((st = p->alloc(&d_nch, nwc, s))) return st;
+  if ((st = p->alloc(&d_chfirst, (size_t)nwc + 1, s))) return st;
+  if ((st = p->alloc((char**)&chtmp, scan_tmp_bytes(nwc), s))) return st;
+  launch_uwin_chunks(p->pp, nwc, wcols, p->d_u, d_nch, s);
+  launch_scan(d_nch, nwc, d_chfirst, &p->d_sum->total, &p->d_sum->err, chtmp, s);
+  if ((st = sync_summary(p, s))) return st;
+  if ((st = check_device_err(p))) return st;
+  const long long nchunks = p->h_sum->total;
+  if (nchunks > INT_MAX / 2) return set_error(SPKADD_ERR_OVERFLOW, "too many window chunks (%lld)", nchunks);
+  if ((st = p->alloc(&d_chcol, (size_t)nchunks, s))) return st;
+  launch_uwin_chfill(nwc, d_chfirst, d_chcol, s);
   p->levels = 0;
   for (;;) {
     HIP_TRY(hipMemsetAsync(p->d_cntin, 0, (size_t)W * sizeof(int), s));
     {
       TraceScope t(p, "uwin_hist", s);
-      launch_uwin_hist(p->pp, p->d_cp, p->d_ri, nwc, wcols, p->d_wfirst, p->d_brow, p->d_cntin, s);
+      launch_uwin_hist(p->pp, p->d_cp, p->d_ri, (int)nchunks, wcols, p->d_wfirst, p->d_brow, d_chfirst, d_chcol,
+                       p->d_cntin, s);
     }
     HIP_TRY(hipMemsetAsync(&p->d_sum->pad, 0, 2 * sizeof(int), s));  // pad and max_span
     {
@@ -671,15 +686,14 @@ spkadd_status build_windows_unsorted(spkadd_plan_s* p, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(d_gcur, d_boff, (size_t)W * sizeof(int), hipMemcpyDeviceToDevice, s));
   {
     TraceScope t(p, "uwin_scatter", s);
-    launch_uwin_scatter(p->pp, p->d_cp, p->d_ri, nwc, wcols, p->d_wfirst, p->d_brow, d_boff, d_gcur, p->d_ubrows,
-                        p->d_ubsrc, s);
+    launch_uwin_scatter(p->pp, p->d_cp, p->d_ri, (int)nchunks, wcols, p->d_wfirst, p->d_brow, d_chfirst, d_chcol,
+                        d_gcur, p->d_ubrows, p->d_ubsrc, s);
   }
   const void* tab[2] = {p->d_ubrows, p->d_ubvals};
   launch_put_ptrs(tab, 2, p->d_utab, nullptr, nullptr, s);
   HIP_TRY(hipGetLastError());
-  p->release(tmp, s);
-  p->release(d_boff, s);
-  p->release(d_gcur, s);
+  for (void* x : {tmp, (void*)d_boff, (void*)d_gcur, (void*)d_nch, (void*)d_chfirst, (void*)d_chcol, chtmp})
+    p->release(x, s);
   if ((st = p->alloc(&p->d_win_cnt, W, s))) return st;
   if ((st = p->alloc(&p->d_win_off, W, s))) return st;
   if ((st = p->alloc(&p->d_wrec, W, s))) return st;

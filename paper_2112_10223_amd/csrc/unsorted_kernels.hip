@@ -12,7 +12,7 @@
 namespace spk {
 
 constexpr int UW_THREADS = 256;
-constexpr int UW_LDS_WIN = 4096;  // a column with at most this many windows counts / places them in LDS
+constexpr int UW_LDS_WIN = 4096;  // a column with at most this many windows counts them in LDS
 constexpr int UW_LDS_K = 1024;    // at most this many inputs: one flat pass over the column's entries
 
 // The window of `row` among a column's P windows, whose boundary rows are bro[0..P]
@@ -27,40 +27,75 @@ __device__ __forceinline__ int window_of(const int* __restrict__ bro, int P, int
   return lo;
 }
 
-// One block per window column.  SCATTER = false: cnt[w] = entries of window w.
-// SCATTER = true: each entry goes to slot cursor(w)++ of its window's bucket, which
-// starts at boff[w] (cursors in LDS, or in `gcur`, preset to boff, for columns with
-// more windows than LDS holds).
+// Work units of the window passes: chunks of UW_CHUNK entries of a column's
+// concatenated input segments (one chunk per column when it has more inputs than the
+// on-chip segment table), so that a long column is spread over many workgroups.
+constexpr int UW_CHUNK = 4096;
+constexpr int UW_EPT = UW_CHUNK / UW_THREADS;  // entries of a chunk per thread, kept in registers
+
+__global__ __launch_bounds__(256) void k_uwin_nch(PlanParams p, int n_wcols, const int* __restrict__ wcols,
+                                                  const int* __restrict__ u, int* __restrict__ nch) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= n_wcols) return;
+  const int uc = u[wcols[c]];
+  nch[c] = p.k <= UW_LDS_K ? max((uc + UW_CHUNK - 1) / UW_CHUNK, 1) : 1;
+}
+
+__global__ __launch_bounds__(256) void k_uwin_chfill(int n_wcols, const int* __restrict__ chfirst,
+                                                     int* __restrict__ chcol) {
+  const int c = blockIdx.x;
+  if (c >= n_wcols) return;
+  for (int t = chfirst[c] + threadIdx.x; t < chfirst[c + 1]; t += 256) chcol[t] = c;
+}
+
+// One workgroup per chunk.  SCATTER = false: cnt[w] += entries of window w in the
+// chunk.  SCATTER = true: the chunk reserves a range of each window's bucket (gcur:
+// the next free slot of each bucket, preset to its start) and places its entries
+// there: the row and the entry's (input, position).  Windows are counted in LDS
+// when the column has at most UW_LDS_WIN of them, else by global atomics per entry.
 template <bool SCATTER>
 __global__ __launch_bounds__(UW_THREADS) void k_uwin_pass(PlanParams p, const int* const* __restrict__ cp,
                                                         const int* const* __restrict__ ri,
                                                         const int* __restrict__ wcols, const int* __restrict__ wfirst,
-                                                        const int* __restrict__ brow, int* __restrict__ cnt,
-                                                        const int* __restrict__ boff, int* __restrict__ gcur,
-                                                        int* __restrict__ brows, long long* __restrict__ bsrc) {
+                                                        const int* __restrict__ brow,
+                                                        const int* __restrict__ chfirst,
+                                                        const int* __restrict__ chcol, int* __restrict__ cnt,
+                                                        int* __restrict__ gcur, int* __restrict__ brows,
+                                                        long long* __restrict__ bsrc) {
   __shared__ int segp[UW_LDS_K + 1];  // exclusive prefix of the segment lengths
   __shared__ int segs[UW_LDS_K];      // segment starts
-  __shared__ int lc[UW_LDS_WIN];      // per-window counts or cursors
+  __shared__ int lc[UW_LDS_WIN];      // per-window counts, then cursors
+  __shared__ int lbro[UW_LDS_WIN + 1];
   __shared__ int red[UW_THREADS / 64 + 1];
-  const int c = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
+  const int c = chcol[blockIdx.x], chunk = blockIdx.x - chfirst[c];
   const int j = wcols[c], w0 = wfirst[c], P = wfirst[c + 1] - w0;
   const int* bro = brow + w0 + c;
   const bool lds_win = P <= UW_LDS_WIN;
-  if (lds_win)
-    for (int q = tid; q < P; q += UW_THREADS) lc[q] = SCATTER ? boff[w0 + q] : 0;
-  auto place = [&](int i, int pos) {
+  if (lds_win) {
+    for (int q = tid; q <= P; q += UW_THREADS) lbro[q] = bro[q];
+    for (int q = tid; q < P; q += UW_THREADS) lc[q] = 0;
+  }
+  auto win = [&](int row) { return lds_win ? window_of(lbro, P, row) : window_of(bro, P, row); };
+  auto put = [&](int slot, int row, int i, int pos) {
+    brows[slot] = row;
+    bsrc[slot] = ((long long)i << 32) | (unsigned)pos;
+  };
+  // the first pass counts (or, without LDS counters, does all the work); the second
+  // places the entries of an LDS-counted chunk
+  auto first = [&](int i, int pos) {
     const int row = ri[i][pos];
-    const int q = window_of(bro, P, row);
-    if (!SCATTER) {
-      atomicAdd(lds_win ? &lc[q] : &cnt[w0 + q], 1);
-    } else {
-      const int slot = atomicAdd(lds_win ? &lc[q] : &gcur[w0 + q], 1);
-      brows[slot] = row;
-      bsrc[slot] = ((long long)i << 32) | (unsigned)pos;
-    }
+    const int q = win(row);
+    if (lds_win) atomicAdd(&lc[q], 1);
+    else if (!SCATTER) atomicAdd(&cnt[w0 + q], 1);
+    else put(atomicAdd(&gcur[w0 + q], 1), row, i, pos);
+  };
+  auto second = [&](int i, int pos) {
+    const int row = ri[i][pos];
+    put(atomicAdd(&lc[win(row)], 1), row, i, pos);
   };
   if (p.k <= UW_LDS_K) {
-    // one flat pass over the concatenated segments of all inputs
+    // the column's entries as one concatenated range; this chunk is [e0, e1)
     int carry = 0;
     for (int base = 0; base < p.k; base += UW_THREADS) {
       const int i = base + tid;
@@ -70,32 +105,79 @@ __global__ __launch_bounds__(UW_THREADS) void k_uwin_pass(PlanParams p, const in
         len = max(cp[i][j + 1] - s, 0);
         segs[i] = s;
       }
-      int chunk = 0;
-      const int ex = block_excl_scan<UW_THREADS>(len, red, &chunk);
+      int chunk_sum = 0;
+      const int ex = block_excl_scan<UW_THREADS>(len, red, &chunk_sum);
       if (i < p.k) segp[i] = carry + ex;
-      carry += chunk;
+      carry += chunk_sum;
     }
     if (tid == 0) segp[p.k] = carry;
     __syncthreads();
     int ktop = 0;  // largest power of two <= k - 1
     while ((ktop << 1) <= p.k - 1) ktop = ktop ? ktop << 1 : 1;
     if (p.k == 1) ktop = 0;
-    for (int e = tid; e < carry; e += UW_THREADS) {
-      int lo = 0;
-      for (int step = ktop; step > 0; step >>= 1)
-        if (lo + step < p.k && segp[lo + step] <= e) lo += step;
-      place(lo, segs[lo] + (e - segp[lo]));
+    const long long e0l = (long long)chunk * UW_CHUNK;
+    const int e0 = (int)(e0l < carry ? e0l : carry);
+    const int e1 = (int)(e0l + UW_CHUNK < carry ? e0l + UW_CHUNK : carry);
+    // every entry of the chunk once: row, window and source kept in registers for the
+    // placement after the reservation (clamped index: no guard on the loads)
+    int rowv[UW_EPT], qv[UW_EPT], iv[UW_EPT], posv[UW_EPT];
+    if (e0 < e1) {  // (uniform)
+#pragma unroll
+      for (int t = 0; t < UW_EPT; ++t) {
+        const int e = min(e0 + tid + t * UW_THREADS, e1 - 1);
+        int lo = 0;
+        for (int step = ktop; step > 0; step >>= 1)
+          if (lo + step < p.k && segp[lo + step] <= e) lo += step;
+        iv[t] = lo;
+        posv[t] = segs[lo] + (e - segp[lo]);
+        rowv[t] = ri[lo][posv[t]];
+      }
+#pragma unroll
+      for (int t = 0; t < UW_EPT; ++t) {
+        const bool mine = e0 + tid + t * UW_THREADS < e1;
+        qv[t] = mine ? win(rowv[t]) : -1;
+        if (!mine) continue;
+        if (lds_win) atomicAdd(&lc[qv[t]], 1);
+        else if (!SCATTER) atomicAdd(&cnt[w0 + qv[t]], 1);
+        else put(atomicAdd(&gcur[w0 + qv[t]], 1), rowv[t], iv[t], posv[t]);
+      }
+    }
+    __syncthreads();
+    if (lds_win) {
+      if (!SCATTER) {
+        for (int q = tid; q < P; q += UW_THREADS)
+          if (lc[q]) atomicAdd(&cnt[w0 + q], lc[q]);
+      } else {
+        for (int q = tid; q < P; q += UW_THREADS)
+          if (lc[q]) lc[q] = atomicAdd(&gcur[w0 + q], lc[q]);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < UW_EPT; ++t)
+          if (qv[t] >= 0) put(atomicAdd(&lc[qv[t]], 1), rowv[t], iv[t], posv[t]);
+      }
     }
   } else {
+    // more inputs than the segment table: one chunk per column, input by input
     __syncthreads();
     for (int i = 0; i < p.k; ++i) {
       const int s = cp[i][j], e = cp[i][j + 1];
-      for (int pos = s + tid; pos < e; pos += UW_THREADS) place(i, pos);
+      for (int pos = s + tid; pos < e; pos += UW_THREADS) first(i, pos);
     }
-  }
-  if (!SCATTER && lds_win) {
     __syncthreads();
-    for (int q = tid; q < P; q += UW_THREADS) cnt[w0 + q] = lc[q];
+    if (lds_win) {
+      if (!SCATTER) {
+        for (int q = tid; q < P; q += UW_THREADS)
+          if (lc[q]) atomicAdd(&cnt[w0 + q], lc[q]);
+      } else {
+        for (int q = tid; q < P; q += UW_THREADS)
+          if (lc[q]) lc[q] = atomicAdd(&gcur[w0 + q], lc[q]);
+        __syncthreads();
+        for (int i = 0; i < p.k; ++i) {
+          const int s = cp[i][j], e = cp[i][j + 1];
+          for (int pos = s + tid; pos < e; pos += UW_THREADS) second(i, pos);
+        }
+      }
+    }
   }
 }
 
@@ -122,19 +204,31 @@ __global__ __launch_bounds__(256) void k_uwin_gather(long long total, const long
   bvals[t] = reinterpret_cast<const V*>(va[(int)(s >> 32)])[(unsigned)s];
 }
 
-void launch_uwin_hist(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int n_wcols,
-                      const int* d_wcols, const int* d_wfirst, const int* d_brow, int* d_cnt, hipStream_t s) {
+void launch_uwin_chunks(const PlanParams& p, int n_wcols, const int* d_wcols, const int* d_u, int* d_nch,
+                        hipStream_t s) {
   if (n_wcols <= 0) return;
-  k_uwin_pass<false><<<n_wcols, UW_THREADS, 0, s>>>(p, d_cp, d_ri, d_wcols, d_wfirst, d_brow, d_cnt, nullptr,
-                                                    nullptr, nullptr, nullptr);
+  k_uwin_nch<<<(n_wcols + 255) / 256, 256, 0, s>>>(p, n_wcols, d_wcols, d_u, d_nch);
 }
 
-void launch_uwin_scatter(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int n_wcols,
-                         const int* d_wcols, const int* d_wfirst, const int* d_brow, const int* d_boff, int* d_gcur,
-                         int* d_brows, long long* d_bsrc, hipStream_t s) {
+void launch_uwin_chfill(int n_wcols, const int* d_chfirst, int* d_chcol, hipStream_t s) {
   if (n_wcols <= 0) return;
-  k_uwin_pass<true><<<n_wcols, UW_THREADS, 0, s>>>(p, d_cp, d_ri, d_wcols, d_wfirst, d_brow, nullptr, d_boff,
-                                                   d_gcur, d_brows, d_bsrc);
+  k_uwin_chfill<<<n_wcols, 256, 0, s>>>(n_wcols, d_chfirst, d_chcol);
+}
+
+void launch_uwin_hist(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int n_chunks,
+                      const int* d_wcols, const int* d_wfirst, const int* d_brow, const int* d_chfirst,
+                      const int* d_chcol, int* d_cnt, hipStream_t s) {
+  if (n_chunks <= 0) return;
+  k_uwin_pass<false><<<n_chunks, UW_THREADS, 0, s>>>(p, d_cp, d_ri, d_wcols, d_wfirst, d_brow, d_chfirst, d_chcol,
+                                                     d_cnt, nullptr, nullptr, nullptr);
+}
+
+void launch_uwin_scatter(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int n_chunks,
+                         const int* d_wcols, const int* d_wfirst, const int* d_brow, const int* d_chfirst,
+                         const int* d_chcol, int* d_gcur, int* d_brows, long long* d_bsrc, hipStream_t s) {
+  if (n_chunks <= 0) return;
+  k_uwin_pass<true><<<n_chunks, UW_THREADS, 0, s>>>(p, d_cp, d_ri, d_wcols, d_wfirst, d_brow, d_chfirst, d_chcol,
+                                                    nullptr, d_gcur, d_brows, d_bsrc);
 }
 
 void launch_uwin_bpos(int n_windows, const int* d_win_c, const int* d_wfirst, const int* d_boff, int* d_bpos,
