@@ -375,6 +375,29 @@ def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 5) -> float:
     return round(2 * nbytes / (best * 1e-3) / 1e9, 1)
 
 
+def compare_algorithms(m, cps, ris, vas, nnz_out, hash_ms, reps=3):
+    """The paper's algorithm comparison on this workload, on the GPU: the hash k-way
+    sum (the timed steps above) against the k-way heap merge (Algorithm 3) and the
+    2-way tree (Section II-B), each a whole call with its allocations, mean of `reps`
+    after one warm-up; nnz(B) checked against the hash result."""
+    import torch
+    from paper_2112_10223_amd import baselines
+    res = {"hash_ms": round(hash_ms, 4)}
+    for name, fn in (("heap", baselines.heap_add), ("tree", baselines.tree_add)):
+        c, _, _ = fn(m, cps, ris, vas)
+        torch.cuda.synchronize()
+        ok = int(c[-1].item()) == nnz_out
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn(m, cps, ris, vas)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        res[f"{name}_ms"] = round(ms, 4)
+        res[f"{name}_nnz_agrees"] = ok
+        res[f"{name}_over_hash"] = round(ms / hash_ms, 2)
+    return res
+
+
 def reversed_columns(batch):
     """The same matrices with every column's entries in descending row order."""
     import workloads
@@ -405,6 +428,8 @@ def main() -> int:
                     help="every input column reversed (descending rows), planned with SPKADD_FLAG_UNSORTED_IN")
     ap.add_argument("--unsorted-out", action="store_true",
                     help="rows of each output column in any order (hash accumulators skip their sort)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the comparison with the heap-merge and 2-way-tree baselines")
     ap.add_argument("--batched", type=int, default=400,
                     help="requests of the batched-vs-plain measurement (0 = skip)")
     args = ap.parse_args()
@@ -607,6 +632,8 @@ def main() -> int:
     }
     if tuned is not None:
         out["tune"] = tuned
+    if not args.no_compare and not args.unsorted_in and k <= 128:
+        out["algorithms"] = compare_algorithms(m, cps, ris, vas, nnz_out, ms_per_step)
     if args.batched > 0:
         out["served"], out["batched"] = measure_batched(args.batched)
     if not args.no_cpu_baseline:

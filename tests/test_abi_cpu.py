@@ -82,3 +82,19 @@ def test_batch_argument_checks_without_gpu():
     assert L.spkadd_batch_results(None, None, None) == binding.SPKADD_ERR_INVALID
     assert L.spkadd_batch_destroy(None) == binding.SPKADD_OK
     assert b"NULL" in L.spkadd_last_error() or len(L.spkadd_last_error()) > 0
+
+
+def test_heap_baseline_argument_errors(L):
+    """spkadd_heap_add rejects bad arguments on the host, before any device work."""
+    import ctypes
+    from paper_2112_10223_amd import baselines, binding
+    f = baselines._heap_fn()
+    nnz = ctypes.c_int64(0)
+    arr = (ctypes.c_void_p * 1)(ctypes.c_void_p(0x1000))
+    out = ctypes.c_void_p(0x2000)
+    assert f(10, 10, 0, arr, arr, arr, 0, out, out, out, 0, ctypes.byref(nnz), None) == binding.SPKADD_ERR_INVALID
+    assert f(10, 10, baselines.HEAP_MAX_K + 1, arr, arr, arr, 0, out, out, out, 0, ctypes.byref(nnz),
+             None) == binding.SPKADD_ERR_INVALID
+    assert f(-1, 10, 1, arr, arr, arr, 0, out, out, out, 0, ctypes.byref(nnz), None) == binding.SPKADD_ERR_INVALID
+    assert f(10, 10, 1, arr, arr, arr, 5, out, out, out, 0, ctypes.byref(nnz), None) == binding.SPKADD_ERR_INVALID
+    assert f(10, 10, 1, arr, arr, arr, 0, out, None, None, 4, ctypes.byref(nnz), None) == binding.SPKADD_ERR_INVALID
