@@ -52,6 +52,7 @@ struct PlanParams {
   int force_bin;    // -1 auto
   float win_fill;   // target window input count = cap_in * win_fill
   int unsorted_in;  // input columns may be unsorted (validation checks only the row range)
+  int win_min;      // fewest windows of a window column (each then at most the bitmap's rows)
 };
 
 // Summary written by the plan kernels; the host reads it from a pinned slot.

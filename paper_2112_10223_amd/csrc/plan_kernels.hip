@@ -217,8 +217,8 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_bin_scatter(PlanParams p, cons
   }
 }
 
-// Initial number of windows of each window column: P = ceil(u / (cap_in * fill)),
-// clamped to [1, m]; exclusive scan into wfirst[0..n_wcols].  One block.
+// Initial number of windows of each window column: P = ceil(u / (cap_in * fill)), at
+// least win_min, clamped to [1, m]; exclusive scan into wfirst[0..n_wcols].  One block.
 __global__ __launch_bounds__(1024) void k_win_scan(PlanParams p, const int* __restrict__ list,
                                                    const int* __restrict__ binoff, const int* __restrict__ u,
                                                    int* __restrict__ wfirst, PlanSummary* __restrict__ sum) {
@@ -233,6 +233,7 @@ __global__ __launch_bounds__(1024) void k_win_scan(PlanParams p, const int* __re
     if (c < n_wcols) {
       const int uj = u[wcols[c]];
       pc = (long long)ceil((double)uj / (target > 1.0 ? target : 1.0));
+      if (pc < p.win_min) pc = p.win_min;
       if (pc < 1) pc = 1;
       if (pc > p.m) pc = p.m;
     }

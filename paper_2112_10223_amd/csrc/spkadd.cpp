@@ -893,6 +893,11 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
   p->pp.win_fill = o.window_fill > 0 ? o.window_fill : kDefaultFill;
   p->unsorted_in = (o.flags & SPKADD_FLAG_UNSORTED_IN) != 0;
   p->pp.unsorted_in = p->unsorted_in ? 1 : 0;
+  // windows no wider than the workgroup bitmap, so that none falls back to hash
+  // tables (unless hash tables are asked for)
+  p->pp.win_min = 1;
+  if (o.accum_mode != SPKADD_ACCUM_HASH && o.hash_mode == 0 && m > bitmap_wg_span_max())
+    p->pp.win_min = (int)(((long long)m + bitmap_wg_span_max() - 1) / bitmap_wg_span_max());
   for (int b = BIN_W1; b <= BIN_W16; ++b) {
     p->ts_sym[b] = table_slots(64 * wave_bin_E(b), p->alpha_sym_q);
     p->ts_num[b] = table_slots(64 * wave_bin_E(b), p->alpha_num_q);
