@@ -56,7 +56,7 @@ typedef enum spkadd_status {
   SPKADD_ERR_HIP = 3,         /* a HIP runtime call failed; the plan is unusable */
   SPKADD_ERR_STATE = 4,       /* calls out of order (numeric before symbolic) */
   SPKADD_ERR_OVERFLOW = 5,    /* a count does not fit int32 (u_j, nnz(B)) */
-  SPKADD_ERR_UNSUPPORTED = 6  /* a size this build does not handle (see spkadd_plan) */
+  SPKADD_ERR_UNSUPPORTED = 6  /* a size the library does not handle (see spkadd_plan) */
 } spkadd_status;
 
 typedef enum spkadd_dtype { SPKADD_F32 = 0, SPKADD_F64 = 1 } spkadd_dtype;
