@@ -88,8 +88,8 @@ void lds_layout_bitmap_wg(bool numeric, int vbytes, int k, int span_max, int cap
   a.off_adjv = off;
   if (numeric) off += k * 8;
   off = align16(off);
-  a.off_mark = off;  // segment-start mask (64 words), its per-word prefix (64 ints), input of each non-empty segment (k ints)
-  off += 64 * 8 + 64 * 4 + k * 4;
+  a.off_mark = off;  // segment-start mask of the units whose entries fit registers
+  off += seg_mask_bytes(k);
   a.slice_bytes = align16(off);
   a.wg_span_max = span_max;
   a.wg_cap = cap;

@@ -20,6 +20,7 @@ __device__ __forceinline__ void bitmap_wg_unit(const KArgs& a, unsigned char* sm
   if (span > a.wg_span_max) return;  // another kernel's unit (uniform)
   unsigned* bm = reinterpret_cast<unsigned*>(smem);
   static_assert(G == 2 || G == 4, "prefix groups of 2 or 4 words");
+  static_assert(NT * EW <= SEG_MASK_UNITS, "the segment mask covers every in-register entry");
   unsigned short* pw = reinterpret_cast<unsigned short*>(smem + a.off_pre);  // set bits below each word group
   int* P = reinterpret_cast<int*>(smem + a.off_P);
   long long* adj = reinterpret_cast<long long*>(smem + a.off_adj);
@@ -35,51 +36,18 @@ __device__ __forceinline__ void bitmap_wg_unit(const KArgs& a, unsigned char* sm
       cnt = a.colptr_c[j + 1] - o0;
     }
   }
-  // starts of the non-empty segments over the entry positions (a unit whose entries
-  // all fit registers): entry e lies in the non-empty segment numbered (starts at
-  // positions <= e) - 1, from one mask word and a per-word prefix, and nzmap turns
-  // that number into the input, in place of a binary search over P
-  unsigned long long* smask = reinterpret_cast<unsigned long long*>(smem + a.off_mark);
-  int* mpre = reinterpret_cast<int*>(smem + a.off_mark + 64 * 8);
-  int* nzmap = mpre + 64;
+  unsigned char* sm = smem + a.off_mark;  // segment starts (a unit whose entries fit registers)
   if (tid < 64) {
     const int u = build_meta<NUM, V>(a, j, WIN, blo, P, adj, adjv);
     if (tid == 0) info = u;
-    if (u <= NT * EW) {  // (uniform in this wavefront)
-      smask[tid] = 0ull;
-      wave_sync();
-      int rc = 0;
-      for (int base = 0; base < a.k; base += 64) {
-        const int i = base + tid;
-        int s0 = 0, s1 = 0;
-        if (i < a.k) {
-          s0 = P[i];
-          s1 = i + 1 < a.k ? P[i + 1] : u;
-        }
-        const int nz = s1 > s0 ? 1 : 0;
-        const int incl = wave_scan_add(nz);
-        if (nz) {
-          atomicOr(&smask[s0 >> 6], 1ull << (s0 & 63));
-          nzmap[rc + incl - 1] = i;
-        }
-        rc += readlane(incl, 63);
-      }
-      wave_sync();
-      const int cw = __popcll(smask[tid]);
-      mpre[tid] = wave_scan_add(cw) - cw;
-    }
+    if (u <= NT * EW) build_seg_mask(P, a.k, u, sm);  // (uniform in this wavefront)
   }
   const int ngrp = (span + 32 * G - 1) / (32 * G);
   for (int w = tid; w < G * ngrp; w += NT) bm[w] = 0u;
   __syncthreads();
   const int u = info;
   const bool one = u <= NT * EW;  // every entry of the unit in registers at once
-  auto seg_at = [&](int e) -> int {
-    if (!one) return seg_of(P, a.k, a.ktop, e);
-    const int w = e >> 6, b = e & 63;
-    const unsigned long long upto = b == 63 ? ~0ull : (2ull << b) - 1ull;
-    return nzmap[mpre[w] + (int)__popcll(smask[w] & upto) - 1];
-  };
+  auto seg_at = [&](int e) -> int { return one ? seg_fast(sm, e) : seg_of(P, a.k, a.ktop, e); };
   int rows[EW];
   V vals[EW];
   bool first[EW];

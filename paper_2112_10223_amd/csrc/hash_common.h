@@ -104,6 +104,50 @@ __device__ __forceinline__ int seg_of(const int* P, int k, int ktop, int e) {
   return lo;
 }
 
+// Segment lookup in O(1) for a unit of at most SEG_MASK_UNITS entries: the starts of
+// its non-empty segments are bits of a 64-word mask over the entry positions; entry e
+// lies in the non-empty segment numbered (starts at positions <= e) - 1, which nzmap
+// turns into the input.  Layout at `m` (seg_mask_bytes(k)): mask, per-word prefix
+// counts (64 ints), nzmap (k ints).  Built by one wavefront after build_meta wrote P.
+constexpr int SEG_MASK_UNITS = 64 * 64;
+__host__ __device__ constexpr int seg_mask_bytes(int k) { return 64 * 8 + 64 * 4 + k * 4; }
+
+__device__ __forceinline__ void build_seg_mask(const int* P, int k, int u, unsigned char* m) {
+  unsigned long long* smask = reinterpret_cast<unsigned long long*>(m);
+  int* mpre = reinterpret_cast<int*>(m + 64 * 8);
+  int* nzmap = mpre + 64;
+  const int lane = lane_id();
+  smask[lane] = 0ull;
+  wave_sync();
+  int rc = 0;
+  for (int base = 0; base < k; base += 64) {
+    const int i = base + lane;
+    int s0 = 0, s1 = 0;
+    if (i < k) {
+      s0 = P[i];
+      s1 = i + 1 < k ? P[i + 1] : u;
+    }
+    const int nz = s1 > s0 ? 1 : 0;
+    const int incl = wave_scan_add(nz);
+    if (nz) {
+      atomicOr(&smask[s0 >> 6], 1ull << (s0 & 63));
+      nzmap[rc + incl - 1] = i;
+    }
+    rc += readlane(incl, 63);
+  }
+  wave_sync();
+  const int cw = __popcll(smask[lane]);
+  mpre[lane] = wave_scan_add(cw) - cw;
+}
+
+__device__ __forceinline__ int seg_fast(const unsigned char* m, int e) {
+  const unsigned long long* smask = reinterpret_cast<const unsigned long long*>(m);
+  const int* mpre = reinterpret_cast<const int*>(m + 64 * 8);
+  const int w = e >> 6, b = e & 63;
+  const unsigned long long upto = b == 63 ? ~0ull : (2ull << b) - 1ull;
+  return mpre[64 + mpre[w] + (int)__popcll(smask[w] & upto) - 1];
+}
+
 // One LSD pass over src[lo, hi) of a wavefront: stable scatter into dst by the digit
 // ((key - rlo) >> sh) & mask.  `off` holds the running output offset per digit.
 // `match` (256 lane masks) must be all zero on entry and is all zero on exit.

@@ -217,9 +217,11 @@ __global__ __launch_bounds__(NT) void k_hash_wg(KArgs a, const int* __restrict__
   int* P = (int*)(smem + a.off_P);
   long long* adj = (long long*)(smem + a.off_adj);
   long long* adjv = (long long*)(smem + a.off_adjv);
+  unsigned char* sm = smem + a.off_mark;
   if (tid < 64) {
     const int u = build_meta<NUM, V>(a, j, WIN, blo, P, adj, adjv);
     if (tid == 0) info = u;
+    if (u <= SEG_MASK_UNITS) build_seg_mask(P, a.k, u, sm);  // (uniform in this wavefront)
   }
   int cnt = 0, o0 = 0, TS;
   if (NUM) {
@@ -256,7 +258,7 @@ __global__ __launch_bounds__(NT) void k_hash_wg(KArgs a, const int* __restrict__
     for (int t = 0; t < EW; ++t) {
       const int e = cb + tid + NT * t;
       if (e < u) {
-        const int sg = seg_of(P, a.k, a.ktop, e);
+        const int sg = u <= SEG_MASK_UNITS ? seg_fast(sm, e) : seg_of(P, a.k, a.ktop, e);
         rows[t] = gload<int>(adj[sg] + 4LL * e);
         if (NUM) vals[t] = gload<V>(adjv[sg] + (long long)sizeof(V) * e);
       }
@@ -355,6 +357,11 @@ void lds_layout(int bin, bool numeric, int vbytes, int k, int ts_max, KArgs& a) 
   off += k * 8;
   a.off_adjv = off;
   if (numeric) off += k * 8;
+  if (!is_wave_bin(bin)) {  // workgroup units: the segment-start mask
+    off = align_up(off, 16);
+    a.off_mark = off;
+    off += seg_mask_bytes(k);
+  }
   a.slice_bytes = align_up(off, 16);
   a.ts_max = ts_max;
 }
