@@ -299,3 +299,49 @@ def test_batch_argument_errors():
         bt.results()  # no run yet
     torch.cuda.synchronize()
     bt.close()
+
+
+def _stream_batches(seed, count, values, max_nnz=1 << 19):
+    """Requests of the batched workload's distribution (k ~ U{2..64}, m and n
+    log-uniform in [256, 65536], per-matrix density log-uniform in [1e-4, 1e-2]),
+    requests above max_nnz expected input entries redrawn, plus fixed requests at the
+    edge of the one-input-per-lane layout (k = 63 and 64) in wave, workgroup and
+    too-large columns."""
+    out = workloads.request_stream(count, seed=seed, max_nnz=max_nnz, values=values)
+    out += [workloads.er(3000, 50, 64, 5.0, seed=seed + 1, values=values),      # k = 64, u ~ 320
+            workloads.er(60000, 40, 63, 10.0, seed=seed + 2, values=values),    # k = 63, hash wave columns
+            workloads.er(800, 30, 64, 14.0, seed=seed + 3, values=values),      # k = 64, u ~ 900
+            workloads.er(5000, 20, 64, 40.0, seed=seed + 4, values=values),     # k = 64, u ~ 2560: workgroup
+            workloads.er(20000, 12, 64, 100.0, seed=seed + 5, values=values)]   # k = 64, u ~ 6400: too large
+    return out
+
+
+@pytest.mark.parametrize("values", ["int32f", "f32", "f64"])
+def test_batch_request_stream(values):
+    """Requests drawn from the batched workload's own distribution, k up to 64 (and
+    exactly 63 and 64), each against the oracle; the requests the run reports too large
+    go through the one-request path and are checked as well."""
+    import torch
+    from paper_2112_10223_amd import binding
+    note(f"batch request stream values={values}")
+    batches = _stream_batches(81, 40, values)
+    assert max(b.k for b in batches) == 64
+    reqs = _requests(batches)
+    dtype = binding.SPKADD_F64 if values == "f64" else binding.SPKADD_F32
+    bt = _batch(dtype, len(batches), sum(b.n for b in batches), sum(b.k for b in batches))
+    bt.run(reqs, use_graph=True)
+    nnz, st = bt.results()
+    torch.cuda.synchronize()
+    exact = values.startswith("int")
+    big = [i for i, s in enumerate(st) if s == binding.SPKADD_REQ_TOO_LARGE]
+    assert len(batches) - 1 in big
+    ok = [i for i in range(len(batches)) if i not in big]
+    _check_all([batches[i] for i in ok], [reqs[i] for i in ok], [nnz[i] for i in ok], [st[i] for i in ok], exact)
+    for i in big:
+        b = batches[i]
+        cps, ris, vas = to_device(b)
+        cp, r, v = binding.spkadd(b.m, cps, ris, vas)
+        torch.cuda.synchronize()
+        got = (cp.cpu().numpy().astype(np.int64), r.cpu().numpy(), v.cpu().numpy())
+        assert_matches(b, got, oracle.spkadd(b), exact_values=exact)
+    bt.close()

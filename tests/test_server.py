@@ -137,3 +137,67 @@ def test_server_errors():
         srv.release(tk)  # already released
     torch.cuda.synchronize()
     srv.close()
+
+
+def _stream_mix(seed, count, values):
+    """Requests of the served workload's distribution (k ~ U{2..64}), a bounded sample
+    (expected input entries <= 2^19), plus requests with columns too long for a batched
+    run (they take the one-request lane, row windows included)."""
+    out = workloads.request_stream(count, seed=seed, max_nnz=1 << 19, values=values)
+    out += [workloads.er(65536, 60, 64, 400.0, seed=seed + 1, values=values),   # u ~ 25600: windows
+            workloads.er(20000, 12, 64, 100.0, seed=seed + 2, values=values)]   # u ~ 6400
+    return out
+
+
+@pytest.mark.parametrize("values", ["int32f", "f32"])
+def test_server_request_stream_alone_vs_mix(values):
+    """Every request of a sample of the served workload (k up to 64, large requests
+    in the one-request lane) gives the same result alone and in a concurrent mix:
+    colptr and rows bit-exact, values bit-exact for integer-valued inputs and, for real
+    values, both within the oracle's tolerance (so within twice it of each other)."""
+    import numpy as np
+    from paper_2112_10223_amd import binding
+    note(f"server request stream alone vs mix values={values}")
+    targets = _stream_mix(91, 20, values)
+    others = _stream_mix(92, 30, values)
+    srv = binding.Server(n_streams=2, max_batch=8, max_columns=1 << 17, max_inputs=8 * 64, depth=1)
+    alone = []
+    for b in targets:
+        tk, keep = _submit(srv, b)
+        alone.append(_collect(srv, tk))
+    tickets, keeps = [], []
+
+    def submit_others():
+        for b in others:
+            tk, keep = _submit(srv, b)
+            keeps.append(keep)
+            tickets.append((tk, b))
+
+    th = threading.Thread(target=submit_others)
+    th.start()
+    mine = []
+    for b in targets:
+        tk, keep = _submit(srv, b)
+        keeps.append(keep)
+        mine.append(tk)
+    th.join()
+    exact = values.startswith("int")
+    lanes = []
+    for i, (tk, b) in enumerate(zip(mine, targets)):
+        res, got = _collect(srv, tk)
+        ra, ga = alone[i]
+        assert res["nnz"] == ra["nnz"]
+        assert np.array_equal(got[0], ga[0]) and np.array_equal(got[1], ga[1])
+        ref = oracle.spkadd(b)
+        assert_matches(b, got, ref, exact_values=exact)
+        assert_matches(b, ga, ref, exact_values=exact)
+        if exact:
+            assert np.array_equal(got[2], ga[2])
+        lanes.append(res["path"])
+    assert lanes[-1] == 1 and lanes[-2] == 1 and sum(lanes) < len(lanes)
+    for tk, b in tickets:
+        res, got = _collect(srv, tk)
+        assert_matches(b, got, oracle.spkadd(b), exact_values=exact)
+    info = srv.info()
+    assert info["held_bytes"] == 0
+    srv.close()

@@ -34,9 +34,10 @@ def _opts(**kw):
     return binding.make_opts(flags=flags, **kw)
 
 
-def _shuffled(batch, seed, dup_every=0):
+def _shuffled(batch, seed, dup_every=0, repeats=1):
     """The same entries, each input column in a random order; with dup_every > 0 every
-    dup_every-th non-empty column of each input also repeats its first row."""
+    dup_every-th non-empty column of each input also repeats its first row (`repeats`
+    more times, each copy with the value of the first)."""
     rng = np.random.default_rng(seed)
     cps, rows, vals = [], [], []
     for i in range(batch.k):
@@ -46,8 +47,8 @@ def _shuffled(batch, seed, dup_every=0):
             s, e = cp[j], cp[j + 1]
             r, v = batch.rowidx[i][s:e], batch.vals[i][s:e]
             if dup_every and e > s and j % dup_every == 0:
-                r = np.concatenate([r, r[:1]])
-                v = np.concatenate([v, v[:1]])
+                r = np.concatenate([r, np.repeat(r[:1], repeats)])
+                v = np.concatenate([v, np.repeat(v[:1], repeats)])
             perm = rng.permutation(len(r))
             r_out.append(r[perm])
             v_out.append(v[perm])
@@ -152,3 +153,20 @@ def test_sorted_input_same_result():
     got = run_gpu(b, _opts(force_bin=2, window_cap=256))
     for x, y in zip(ref, got):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("force", [False, True])
+def test_real_values_many_repeats(force):
+    """Real values (N(0,1) on R-MAT rows) with rows repeated within input columns so
+    that an output entry sums more terms than there are inputs (t > k): the values
+    must lie within t * u * sum|a| of the oracle's, through every accumulator and
+    through refined row windows."""
+    note(f"unsorted real values, repeats, windows forced={force}")
+    b = _shuffled(workloads.rmat(12, 8, 3, seed=25, values="normal"), seed=7, dup_every=2, repeats=20)
+    ref = oracle.spkadd(b)
+    assert int(ref.mult.max()) > b.k
+    opts = _opts(force_bin=2, window_cap=256) if force else _opts()
+    got = run_gpu(b, opts, stats=True)
+    assert_matches(b, got[:3], ref)
+    if force:
+        assert got[3]["n_windows"] > 0
