@@ -125,3 +125,102 @@ int64_t oracle_spkadd(int64_t m, int64_t n, int32_t k, const int32_t* const* col
   free(T);
   return nnz;
 }
+
+/*
+ * Ordered sums (the SPKADD_FLAG_ORDERED mode) -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Algorithm 5 (Section II-C) takes the inputs of a column in order i = 1..k and adds
+ * every entry into the slot of its row.  Summed that way in the inputs' own
+ * precision, each output value is the sequential sum of its terms in input order:
+ * c = a_first, then c = c + a_next for each later term, one rounding per addition.
+ * Terms of the same input (a repeated row of an unsorted column) come in their stored
+ * order.  The pattern is the same union as oracle_spkadd's.
+ *
+ * Method: list every (column, row, input, position, value) entry, sort by all four
+ * keys, and fold each run of equal (column, row) left to right in float (dtype 0) or
+ * double (dtype 1).  Arguments as oracle_spkadd (vals required); out_val receives
+ * each sum widened to double (exact), out_mult the number of terms.
+ */
+typedef struct {
+  int64_t col;
+  int64_t pos;
+  int32_t row;
+  int32_t src;
+  double v;
+} oentry_t;
+
+static int cmp_oentry(const void* pa, const void* pb) {
+  const oentry_t* x = (const oentry_t*)pa;
+  const oentry_t* y = (const oentry_t*)pb;
+  if (x->col != y->col) return x->col < y->col ? -1 : 1;
+  if (x->row != y->row) return x->row < y->row ? -1 : 1;
+  if (x->src != y->src) return x->src < y->src ? -1 : 1;
+  if (x->pos != y->pos) return x->pos < y->pos ? -1 : 1;
+  return 0;
+}
+
+int64_t oracle_spkadd_ordered(int64_t m, int64_t n, int32_t k, const int32_t* const* colptr,
+                              const int32_t* const* rowidx, const void* const* vals, int32_t dtype,
+                              const int64_t* cols, int64_t ncols, int64_t* out_colptr, int32_t* out_rowidx,
+                              double* out_val, int32_t* out_mult, int64_t out_cap) {
+  if (m < 0 || n < 0 || k < 1 || !colptr || !rowidx || !out_colptr || !vals) return -1;
+  if (dtype != 0 && dtype != 1) return -1;
+  if (!cols) ncols = n;
+  int64_t count = 0;
+  for (int64_t c = 0; c < ncols; c++) {
+    const int64_t col = cols ? cols[c] : c;
+    if (col < 0 || col >= n) return -1;
+    for (int32_t src = 0; src < k; src++) count += (int64_t)colptr[src][col + 1] - colptr[src][col];
+  }
+  oentry_t* E = (oentry_t*)malloc(sizeof(oentry_t) * (size_t)(count > 0 ? count : 1));
+  if (!E) return -1;
+  int64_t fill = 0;
+  for (int64_t c = 0; c < ncols; c++) {
+    const int64_t col = cols ? cols[c] : c;
+    for (int32_t src = 0; src < k; src++) {
+      for (int64_t at = colptr[src][col]; at < colptr[src][col + 1]; at++) {
+        oentry_t* x = &E[fill++];
+        x->col = c;
+        x->pos = at;
+        x->src = src;
+        x->row = rowidx[src][at];
+        x->v = dtype == 0 ? (double)((const float*)vals[src])[at] : ((const double*)vals[src])[at];
+        if (x->row < 0 || x->row >= m) {
+          free(E);
+          return -1;
+        }
+      }
+    }
+  }
+  qsort(E, (size_t)count, sizeof(oentry_t), cmp_oentry);
+  int64_t out = 0, at = 0;
+  out_colptr[0] = 0;
+  for (int64_t c = 0; c < ncols; c++) {
+    while (at < count && E[at].col == c) {
+      int64_t stop = at + 1;
+      while (stop < count && E[stop].col == c && E[stop].row == E[at].row) stop++;
+      if (out >= out_cap) {
+        free(E);
+        return -2;
+      }
+      double result;
+      if (dtype == 0) {
+        float acc = (float)E[at].v;
+        for (int64_t t = at + 1; t < stop; t++) acc = acc + (float)E[t].v;
+        result = (double)acc;
+      } else {
+        double acc = E[at].v;
+        for (int64_t t = at + 1; t < stop; t++) acc = acc + E[t].v;
+        result = acc;
+      }
+      out_rowidx[out] = E[at].row;
+      out_val[out] = result;
+      if (out_mult) out_mult[out] = (int32_t)(stop - at);
+      out++;
+      at = stop;
+    }
+    out_colptr[c + 1] = out;
+  }
+  free(E);
+  return out;
+}

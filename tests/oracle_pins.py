@@ -191,5 +191,76 @@ def pin_column_subset(lib):
         assert np.array_equal(full.val[a], sub.val[b])
 
 
+# ---- the ordered sum (input order, the inputs' precision) ----
+def pin_ordered_hand(lib):
+    """Worked by hand in binary32 / binary64 round-to-nearest-even.  With u the unit
+    roundoff (2^-24 or 2^-53): 1 + u is a tie between 1 and 1 + 2u and rounds to the
+    even 1, so the input order (1, u, u) sums to exactly 1; the order (u, u, 1) first
+    gives 2u exactly and then 1 + 2u, which is representable.  The wide sum of either
+    is 1 + 2u."""
+    for dt, u in ((np.float32, 2.0 ** -24), (np.float64, 2.0 ** -53)):
+        # column 0: inputs hold 1, u, u at row 0; column 1: u, u, 1; column 2: only
+        # inputs 1 and 2 store row 3 (3 then -3: an explicit zero stays stored)
+        cp = np.array([[0, 1, 2, 2], [0, 1, 2, 3], [0, 1, 2, 3]], np.int32)
+        rows = [np.array([0, 0], np.int32), np.array([0, 0, 3], np.int32), np.array([0, 0, 3], np.int32)]
+        vals = [np.array([1.0, u], dt), np.array([u, u, 3.0], dt), np.array([u, 1.0, -3.0], dt)]
+        batch = workloads.CSCBatch(4, 3, cp, rows, vals)
+        res = oracle.spkadd_ordered(batch, lib=lib)
+        assert res.colptr.tolist() == [0, 1, 2, 3]
+        assert res.rowidx.tolist() == [0, 0, 3]
+        assert res.val.dtype == dt
+        assert res.val[0] == dt(1.0), res.val[0]
+        assert res.val[1] == dt(1.0 + 2 * u), res.val[1]
+        assert res.val[2] == dt(0.0)
+        assert res.mult.tolist() == [3, 3, 2]
+
+
+def pin_ordered_dense_brute_force(lib, seeds=range(30)):
+    """Dense brute force: each position's running sum kept in a dense array of the
+    inputs' dtype and updated input by input (numpy adds in that dtype)."""
+    for seed in seeds:
+        rng = np.random.default_rng(500 + seed)
+        m, n, k = int(rng.integers(1, 11)), int(rng.integers(1, 11)), int(rng.integers(1, 9))
+        dt = np.float32 if seed % 2 == 0 else np.float64
+        density = float(rng.choice([0.2, 0.5, 0.9]))
+        masks = [rng.random((m, n)) < density for _ in range(k)]
+        # values spread over many binades, so that the order of the additions matters
+        vals = [(rng.uniform(-1, 1, size=(m, n)) * np.exp2(rng.integers(-30, 12, size=(m, n)))).astype(dt)
+                for _ in range(k)]
+        batch = workloads.from_dense(masks, vals)
+        res = oracle.spkadd_ordered(batch, lib=lib)
+        acc = np.zeros((m, n), dt)
+        seen = np.zeros((m, n), bool)
+        for mk, v in zip(masks, vals):
+            first = mk & ~seen
+            later = mk & seen
+            acc[first] = v[first]
+            acc[later] = acc[later] + v[later]
+            seen |= mk
+        for j in range(n):
+            s, e = res.colptr[j], res.colptr[j + 1]
+            rows = np.nonzero(seen[:, j])[0]
+            assert np.array_equal(res.rowidx[s:e], rows), (seed, j)
+            assert np.array_equal(res.val[s:e].view(np.uint8), acc[rows, j].view(np.uint8)), (seed, j)
+
+
+def pin_ordered_agrees_with_plain(lib):
+    """Same pattern and term counts as the plain oracle; the values equal its wide sum
+    for integer-valued inputs and lie within k * u * sum|a| of it otherwise."""
+    for values in ("int32f", "f32", "f64"):
+        batch = workloads.er(400, 200, 9, 12.0, seed=21, values=values)
+        plain = oracle.spkadd(batch, lib=lib)
+        res = oracle.spkadd_ordered(batch, lib=lib)
+        assert np.array_equal(res.colptr, plain.colptr) and np.array_equal(res.rowidx, plain.rowidx)
+        assert np.array_equal(res.mult, plain.mult)
+        if values == "int32f":
+            assert np.array_equal(res.val.astype(np.float64), plain.val.astype(np.float64))
+        else:
+            unit = 2.0 ** -53 if values == "f64" else 2.0 ** -24
+            diff = np.abs(res.val.astype(np.longdouble) - plain.val)
+            assert (diff <= batch.k * np.longdouble(unit) * plain.abs).all()
+
+
 ALL_PINS = [pin_fig1, pin_dense_brute_force, pin_scipy_k2, pin_er_closed_form, pin_invariants,
-            pin_k1_identity, pin_column_subset]
+            pin_k1_identity, pin_column_subset, pin_ordered_hand, pin_ordered_dense_brute_force,
+            pin_ordered_agrees_with_plain]

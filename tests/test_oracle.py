@@ -47,6 +47,12 @@ MUTATIONS = {
                          "for (int32_t i = 0; i + 1 < k; i++) {\n      for (int64_t p"),
     "row_from_wrong_array": ("T[w].row = rowidx[i][p];", "T[w].row = rowidx[0][p % (colptr[0][n] > 0 ? colptr[0][n] : 1)];"),
     "magnitude_signed": ("mag += T[r_end].val < 0 ? -T[r_end].val : T[r_end].val;", "mag += T[r_end].val;"),
+    # the ordered sum
+    "ordered_reverse_inputs": ("if (x->src != y->src) return x->src < y->src ? -1 : 1;",
+                               "if (x->src != y->src) return x->src > y->src ? -1 : 1;"),
+    "ordered_wide_accumulator": ("float acc = (float)E[at].v;", "double acc = E[at].v;"),
+    "ordered_drops_first_term": ("float acc = (float)E[at].v;", "float acc = 0.0f;"),
+    "ordered_f64_in_f32": ("double acc = E[at].v;", "float acc = (float)E[at].v;"),
 }
 
 
