@@ -75,6 +75,17 @@ typedef enum spkadd_dtype { SPKADD_F32 = 0, SPKADD_F64 = 1 } spkadd_dtype;
                                         of device memory per such entry, plus 4 or 8 gathered in
                                         each spkadd_numeric) instead of binary-searching sorted
                                         columns.  Duplicate rows within a column are still summed. */
+#define SPKADD_FLAG_ORDERED 32u      /* every value of B is the sequential sum of its terms in input
+                                        order i = 1..k, one rounding per addition in the values' type
+                                        (the order in which Algorithm 5 visits the inputs of a column,
+                                        Section II-C): c = a_first, then c = c + a for each later term.
+                                        Results are then reproducible bit for bit, whatever the launch.
+                                        spkadd_numeric runs one more pass that re-reads the inputs and
+                                        rewrites the values.  The output is sorted (UNSORTED_OUT is
+                                        ignored).  With SPKADD_FLAG_UNSORTED_IN, spkadd_plan returns
+                                        SPKADD_ERR_UNSUPPORTED; so it does when k is so large that the
+                                        pass's per-unit table of the k inputs does not fit on chip
+                                        (k above about 2700). */
 
 /* opts.force_bin: test hook that routes columns to one accumulator family */
 #define SPKADD_BIN_AUTO (-1)

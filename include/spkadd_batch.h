@@ -62,7 +62,8 @@ typedef struct spkadd_batch_s* spkadd_batch_t;
  *   dtype : value type of every request.
  *   opts  : NULL for defaults; accum_mode, bitmap_ratio and batch_fused_cols apply
  *           (force_bin, windows and load factors do not).
- * Errors: INVALID, OOM, HIP.
+ * Errors: INVALID, OOM, HIP; UNSUPPORTED for SPKADD_FLAG_ORDERED (the ordered sum
+ * runs through spkadd_plan / spkadd_symbolic / spkadd_numeric only).
  */
 spkadd_status spkadd_batch_create(spkadd_batch_t* out, spkadd_dtype dtype, int32_t max_requests,
                                   int64_t max_columns, int64_t max_inputs, const spkadd_opts* opts);

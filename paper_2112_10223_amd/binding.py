@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OOM", 3: "HIP", 4: "STATE", 5: "OVERF
 SPKADD_F32, SPKADD_F64 = 0, 1
 SPKADD_FLAG_VALIDATE, SPKADD_FLAG_TRACE, SPKADD_FLAG_TRACE_NUMERIC, SPKADD_FLAG_UNSORTED_OUT = 1, 2, 4, 8
 SPKADD_FLAG_UNSORTED_IN = 16
+SPKADD_FLAG_ORDERED = 32
 SPKADD_BIN_AUTO, SPKADD_BIN_WAVE, SPKADD_BIN_WG, SPKADD_BIN_WINDOW = -1, 0, 1, 2
 SPKADD_ACCUM_AUTO, SPKADD_ACCUM_HASH, SPKADD_ACCUM_BITMAP = 0, 1, 2
 SPKADD_REQ_OK, SPKADD_REQ_TOO_LARGE, SPKADD_REQ_CAPACITY = 0, 1, 2

@@ -241,6 +241,8 @@ spkadd_status spkadd_batch_create(spkadd_batch_t* out, spkadd_dtype dtype, int32
   if (opts) o = *opts;
   if (o.accum_mode < 0 || o.accum_mode > 2) return fail(SPKADD_ERR_INVALID, "bad accum_mode %d", o.accum_mode);
   if (!(o.bitmap_ratio >= 0.f && o.bitmap_ratio <= 64.f)) return fail(SPKADD_ERR_INVALID, "bad bitmap_ratio");
+  if (o.flags & SPKADD_FLAG_ORDERED)
+    return fail(SPKADD_ERR_UNSUPPORTED, "batched runs do not take SPKADD_FLAG_ORDERED (use spkadd_plan)");
 
   auto* b = new (std::nothrow) spkadd_batch_s();
   if (!b) return fail(SPKADD_ERR_OOM, "host allocation failed");

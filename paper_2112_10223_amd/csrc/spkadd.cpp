@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "ordered.h"
 
 using namespace spk;
 
@@ -360,6 +361,7 @@ constexpr int kMaxCap = 8192;
 constexpr float kDefaultAlphaSym = 0.5f;
 constexpr float kDefaultAlphaNum = 0.5f;
 constexpr float kDefaultFill = 0.75f;
+constexpr int kOrderedWaveCap = 1024;  // output entries of a wave-bin column (u_j <= 1024)
 
 int ktop_of(int k) {
   if (k <= 1) return 0;
@@ -854,6 +856,8 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
   if (!(o.bitmap_ratio >= 0.f && o.bitmap_ratio <= 64.f))
     return set_error(SPKADD_ERR_INVALID, "bitmap_ratio must be in [0, 64]");
   if (o.wave_merge < 0 || o.wave_merge > 1) return set_error(SPKADD_ERR_INVALID, "bad wave_merge %d", o.wave_merge);
+  if ((o.flags & SPKADD_FLAG_ORDERED) && (o.flags & SPKADD_FLAG_UNSORTED_IN))
+    return set_error(SPKADD_ERR_UNSUPPORTED, "SPKADD_FLAG_ORDERED does not take SPKADD_FLAG_UNSORTED_IN");
 
   auto* p = new (std::nothrow) spkadd_plan_s();
   if (!p) return set_error(SPKADD_ERR_OOM, "host allocation failed");
@@ -908,6 +912,12 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
   p->ts_num[BIN_G2] = p->ts_num[BIN_WIN] = table_slots(cap, p->alpha_num_q);
   if (p->ts_num[BIN_G1] > G1_THREADS * 16 || p->ts_num[BIN_G2] > G2_THREADS * 32)
     return fail(set_error(SPKADD_ERR_INVALID, "window_cap / load_factor_num give too large numeric tables"));
+  if (o.flags & SPKADD_FLAG_ORDERED) {
+    const int need = ordered_lds_bytes(k, cap > kOrderedWaveCap ? cap : kOrderedWaveCap, dtype == SPKADD_F64 ? 8 : 4);
+    if (need > max_lds_bytes())
+      return fail(set_error(SPKADD_ERR_UNSUPPORTED, "SPKADD_FLAG_ORDERED with k=%d needs %d bytes of LDS per unit", k,
+                            need));
+  }
 
   spkadd_status st;
   const int nblk = n > 0 ? (n + PLAN_THREADS - 1) / PLAN_THREADS : 1;
@@ -1076,7 +1086,8 @@ spkadd_status spkadd_numeric(spkadd_plan_t p, const void* const* values, int32_t
   }
   KArgs a = base_args(p);
   a.alpha_q = p->alpha_num_q;
-  a.unsorted = (p->opts.flags & SPKADD_FLAG_UNSORTED_OUT) ? 1 : 0;
+  const bool ordered = (p->opts.flags & SPKADD_FLAG_ORDERED) != 0;
+  a.unsorted = (p->opts.flags & SPKADD_FLAG_UNSORTED_OUT) && !ordered ? 1 : 0;
   a.colptr_c = p->colptr_c;
   a.out_r = rowidx_c;
   a.out_v = values_c;
@@ -1094,6 +1105,24 @@ spkadd_status spkadd_numeric(spkadd_plan_t p, const void* const* values, int32_t
       (void)hipGetLastError();
       p->failed = true;
       return set_error(SPKADD_ERR_HIP, "numeric launch (%s): %s", hash_kernel_name(b, true), hipGetErrorString(e));
+    }
+  }
+  if (ordered && p->nnz_c > 0) {
+    // the rows are in place; every value summed again in input order: wave-bin columns
+    // (at most 1024 output entries), then workgroup-bin columns and row windows (at
+    // most window_cap)
+    const bool f64 = p->dtype == SPKADD_F64;
+    const int* wl = p->d_list + p->binoff[BIN_W1];
+    const int nw = p->binoff[BIN_G1] - p->binoff[BIN_W1];
+    const int* gl = p->d_list + p->binoff[BIN_G1];
+    const int ng = p->binoff[BIN_WIN] - p->binoff[BIN_G1];
+    TraceScope t(p, "num_ordered", stream, true);
+    hipError_t e = launch_ordered(a, wl, nw, 0, kOrderedWaveCap, f64, p->n_cu, stream);
+    if (e == hipSuccess) e = launch_ordered(a, gl, ng, p->n_windows, p->pp.cap_in, f64, p->n_cu, stream);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p->failed = true;
+      return set_error(SPKADD_ERR_HIP, "numeric launch (ordered values): %s", hipGetErrorString(e));
     }
   }
   return SPKADD_OK;
