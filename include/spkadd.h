@@ -179,6 +179,39 @@ spkadd_status spkadd_symbolic(spkadd_plan_t plan, int32_t* colptr_c, int64_t* nn
 spkadd_status spkadd_numeric(spkadd_plan_t plan, const void* const* values, int32_t* rowidx_c, void* values_c,
                              hipStream_t stream);
 
+/*
+ * spkadd_sum_noalloc -- B = A_1 + ... + A_k in one call (spkadd_plan, spkadd_symbolic
+ * and spkadd_numeric in turn) that allocates nothing: for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops that must not
+ * allocate, harnesses that forbid hipMalloc).  Every byte of device workspace comes
+ * from one static array of SPKADD_NOALLOC_SCRATCH_BYTES per GPU, held by the library
+ * from first use until the process ends; summaries come back through pageable host
+ * memory after a wait on the stream.  No hipMalloc, hipFree, pinned allocation or
+ * event creation happens inside the call.
+ *   m, n, k, colptr, rowidx, dtype, opts : as spkadd_plan (trace flags are ignored).
+ *   values   : as spkadd_numeric.
+ *   colptr_c : DEVICE int32[n+1], written with colptr(B).
+ *   rowidx_c, values_c : DEVICE arrays of cap_c entries.
+ *   cap_c    : capacity of rowidx_c / values_c in entries.
+ *   nnz_c    : HOST int64 receiving nnz(B).
+ * The call waits on the stream a few times (as spkadd_plan and spkadd_symbolic do);
+ * the numeric pass is still running on the stream when it returns.
+ * The scratch array is shared by every call on a GPU and keeps the last call's
+ * contents (the library clears what it needs): calls on one GPU must be ordered
+ * (one stream, or synchronised) -- calls that overlap on one GPU race.
+ * Errors: as spkadd_plan / spkadd_symbolic / spkadd_numeric; UNSUPPORTED when the
+ * inputs need more workspace than the array holds (about 18 bytes per column plus
+ * 24 per input, and, when some column needs row windows, about 4 k + 48 bytes per
+ * window and refinement level: with 64 MiB, n up to about 3.5 million columns without
+ * windows); INVALID when nnz(B) > cap_c (colptr_c and *nnz_c are then written,
+ * rowidx_c and values_c are not).
+ */
+#define SPKADD_NOALLOC_SCRATCH_BYTES (64u << 20)
+spkadd_status spkadd_sum_noalloc(int32_t m, int32_t n, int32_t k, const int32_t* const* colptr,
+                                 const int32_t* const* rowidx, const void* const* values, spkadd_dtype dtype,
+                                 const spkadd_opts* opts, int32_t* colptr_c, int32_t* rowidx_c, void* values_c,
+                                 int64_t cap_c, int64_t* nnz_c, hipStream_t stream);
+
 /* spkadd_free -- return the plan's workspace to the library cache and release the
  * plan.  The workspace is reused only after the work queued on the plan's last
  * stream is done.  NULL is a no-op. */

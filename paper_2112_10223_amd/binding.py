@@ -103,6 +103,9 @@ def lib():
         L.spkadd_trace_get.restype = ctypes.c_int
         L.spkadd_trace_reset.argtypes = [P]
         L.spkadd_trace_reset.restype = ctypes.c_int
+        L.spkadd_sum_noalloc.argtypes = [I32, I32, I32, P, P, P, ctypes.c_int, ctypes.POINTER(Opts), P, P, P, I64,
+                                         ctypes.POINTER(I64), P]
+        L.spkadd_sum_noalloc.restype = ctypes.c_int
         L.spkadd_batch_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, I32, I64, I64, ctypes.POINTER(Opts)]
         L.spkadd_batch_create.restype = ctypes.c_int
         L.spkadd_batch_run.argtypes = [P, ctypes.POINTER(Request), I32, I32, P]
@@ -254,6 +257,33 @@ def spkadd(m, colptrs, rowidxs, values, opts: Opts | None = None, stream=None):
     finally:
         plan.free()
     return colptr_c, rowidx_c, values_c
+
+
+SPKADD_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def spkadd_sum_noalloc(m, colptrs, rowidxs, values, colptr_c, rowidx_c, values_c, opts: Opts | None = None,
+                       stream=None) -> int:
+    """The no-allocation entry point: plan, symbolic and numeric in one call, the
+    device workspace in the library's static scratch array.  The caller's output
+    tensors hold colptr(B) (n + 1) and up to len(rowidx_c) entries.  Returns nnz(B)."""
+    import torch
+    k = len(colptrs)
+    n = int(colptrs[0].shape[0]) - 1
+    dtype = SPKADD_F64 if values[0].dtype == torch.float64 else SPKADD_F32
+    cp = _ptr_array(colptrs)
+    ri = _ptr_array(rowidxs)
+    va = _ptr_array(values, non_null=True)
+    cap = int(rowidx_c.shape[0])
+    if int(values_c.shape[0]) < cap or int(colptr_c.shape[0]) != n + 1:
+        raise ValueError("output tensors do not match n and the capacity")
+    nnz = ctypes.c_int64(-1)
+    _check(lib().spkadd_sum_noalloc(m, n, k, ctypes.cast(cp, ctypes.c_void_p), ctypes.cast(ri, ctypes.c_void_p),
+                                    ctypes.cast(va, ctypes.c_void_p), dtype,
+                                    ctypes.byref(opts) if opts is not None else None, colptr_c.data_ptr(),
+                                    rowidx_c.data_ptr() if cap else None, values_c.data_ptr() if cap else None,
+                                    cap, ctypes.byref(nnz), _stream_ptr(stream)))
+    return int(nnz.value)
 
 
 class Batch:

@@ -16,6 +16,7 @@
 
 #include "internal.h"
 #include "ordered.h"
+#include "region.h"
 
 using namespace spk;
 
@@ -289,10 +290,29 @@ struct spkadd_plan_s {
   bool sym_done = false;
   // trace
   std::vector<TraceRec> trace;
+  // region mode (the no-allocation entry point): every workspace array is carved
+  // from one caller-given device region, never returned, and the summaries are read
+  // into this pageable host copy after a wait on the stream
+  bool region_mode = false;
+  char* region = nullptr;
+  size_t region_bytes = 0, region_used = 0;
+  PlanSummary h_sum_local{};
+  hipStream_t sum_stream = nullptr;
 
   template <typename T>
   spkadd_status alloc(T** out, size_t count, hipStream_t s) {
     const size_t bytes = (count ? count : 1) * sizeof(T);
+    if (region_mode) {
+      const size_t off = (region_used + 255) & ~(size_t)255;
+      if (off + bytes > region_bytes)
+        return set_error(SPKADD_ERR_UNSUPPORTED,
+                         "the inputs need more than the %zu bytes of device workspace available here "
+                         "(%zu more requested with %zu in use)",
+                         region_bytes, bytes, region_used);
+      region_used = off + bytes;
+      *out = (T*)(region + off);
+      return SPKADD_OK;
+    }
     void* p = nullptr;
     hipError_t e = WorkspaceCache::get().alloc(&p, bytes, device, s);
     if (e != hipSuccess) {
@@ -430,7 +450,8 @@ constexpr int kErrSentinel = 0x7fffffff;
 spkadd_status copy_summary(spkadd_plan_s* p, hipStream_t s) {
   __atomic_store_n(&p->h_sum->err, kErrSentinel, __ATOMIC_RELAXED);
   HIP_TRY(hipMemcpyAsync(p->h_sum, p->d_sum, sizeof(PlanSummary), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipEventRecord(p->ev_sum, s));
+  p->sum_stream = s;
+  if (!p->region_mode) HIP_TRY(hipEventRecord(p->ev_sum, s));
   return SPKADD_OK;
 }
 
@@ -440,6 +461,10 @@ spkadd_status copy_summary(spkadd_plan_s* p, hipStream_t s) {
 // tens of microseconds late), then polls the copy's event, which completes a few
 // microseconds later.  Each stage falls back to a blocking wait after 20 ms.
 spkadd_status wait_summary(spkadd_plan_s* p) {
+  if (p->region_mode) {  // pageable copy, no event: wait for the stream
+    HIP_TRY(hipStreamSynchronize(p->sum_stream));
+    return SPKADD_OK;
+  }
   using clk = std::chrono::steady_clock;
   const auto limit = std::chrono::milliseconds(20);
   auto t0 = clk::now();
@@ -807,30 +832,19 @@ void release_all(spkadd_plan_s* p) {
   hipStream_t s = p->last_stream;
   for (auto& a : p->allocs) WorkspaceCache::get().release(a.p, a.bytes, p->device, s);
   p->allocs.clear();
-  PinnedPool::get().give(p->h_sum);  // every copy into it was waited for
+  if (!p->region_mode) {
+    PinnedPool::get().give(p->h_sum);  // every copy into it was waited for
+    EventPool::plain().give(p->ev_sum);
+  }
   p->h_sum = nullptr;
-  EventPool::plain().give(p->ev_sum);
   p->ev_sum = nullptr;
 }
 
-}  // namespace
-
-extern "C" {
-
-void spkadd_opts_default(spkadd_opts* o) {
-  if (!o) return;
-  memset(o, 0, sizeof(*o));
-  o->force_bin = SPKADD_BIN_AUTO;
-}
-
-const char* spkadd_last_error(void) { return g_last_error.c_str(); }
-
-spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, const int32_t* const* colptr,
-                          const int32_t* const* rowidx, spkadd_dtype dtype, const spkadd_opts* opts,
-                          hipStream_t stream) {
-  g_last_error.clear();
-  if (!out) return set_error(SPKADD_ERR_INVALID, "out is NULL");
-  *out = nullptr;
+// Argument checks and the planning step into plan p (constructed by the caller, who
+// releases it on an error).
+spkadd_status plan_build(spkadd_plan_s* p, int32_t m, int32_t n, int32_t k, const int32_t* const* colptr,
+                         const int32_t* const* rowidx, spkadd_dtype dtype, const spkadd_opts* opts,
+                         hipStream_t stream) {
   if (m < 0 || n < 0 || m == INT_MAX || n == INT_MAX)
     return set_error(SPKADD_ERR_INVALID, "bad shape m=%d n=%d", m, n);
   if (k < 1) return set_error(SPKADD_ERR_INVALID, "k must be >= 1 (got %d)", k);
@@ -859,17 +873,9 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
   if ((o.flags & SPKADD_FLAG_ORDERED) && (o.flags & SPKADD_FLAG_UNSORTED_IN))
     return set_error(SPKADD_ERR_UNSUPPORTED, "SPKADD_FLAG_ORDERED does not take SPKADD_FLAG_UNSORTED_IN");
 
-  auto* p = new (std::nothrow) spkadd_plan_s();
-  if (!p) return set_error(SPKADD_ERR_OOM, "host allocation failed");
-  auto fail = [&](spkadd_status st) {
-    release_all(p);
-    clear_trace(p);
-    delete p;
-    return st;
-  };
+  auto fail = [](spkadd_status st) { return st; };  // the caller releases the plan
   if (hipGetDevice(&p->device) != hipSuccess) {
     (void)hipGetLastError();
-    delete p;
     return set_error(SPKADD_ERR_HIP, "no HIP device");
   }
   p->m = m;
@@ -921,11 +927,15 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
 
   spkadd_status st;
   const int nblk = n > 0 ? (n + PLAN_THREADS - 1) / PLAN_THREADS : 1;
-  p->h_sum = (PlanSummary*)PinnedPool::get().take();
-  if (!p->h_sum) return fail(set_error(SPKADD_ERR_OOM, "pinned host allocation failed"));
+  if (p->region_mode) {
+    p->h_sum = &p->h_sum_local;
+  } else {
+    p->h_sum = (PlanSummary*)PinnedPool::get().take();
+    if (!p->h_sum) return fail(set_error(SPKADD_ERR_OOM, "pinned host allocation failed"));
+    p->ev_sum = EventPool::plain().take();
+    if (!p->ev_sum) return fail(set_error(SPKADD_ERR_HIP, "event creation failed"));
+  }
   memset(p->h_sum, 0, sizeof(PlanSummary));
-  p->ev_sum = EventPool::plain().take();
-  if (!p->ev_sum) return fail(set_error(SPKADD_ERR_HIP, "event creation failed"));
   // one workspace block for the fixed per-plan buffers
   {
     size_t off = 0;
@@ -962,11 +972,6 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
       p->n_cu = cus;
   }
 
-  std::vector<const void*> host_ptrs(2 * (size_t)k);
-  for (int i = 0; i < k; ++i) {
-    host_ptrs[i] = colptr[i];
-    host_ptrs[k + i] = rowidx[i];
-  }
   auto hipfail = [&](hipError_t e, const char* what) {
     (void)hipGetLastError();
     return fail(set_error(SPKADD_ERR_HIP, "%s: %s", what, hipGetErrorString(e)));
@@ -974,7 +979,17 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
   hipError_t e;
   {
     TraceScope t(p, "put_ptrs", stream);
-    launch_put_ptrs(host_ptrs.data(), 2 * k, (const void**)p->d_cp, p->d_sum, p->d_dummy, stream);
+    if (p->region_mode) {  // (two launches, no host copy of the pointer arrays)
+      launch_put_ptrs((const void* const*)colptr, k, (const void**)p->d_cp, p->d_sum, p->d_dummy, stream);
+      launch_put_ptrs((const void* const*)rowidx, k, (const void**)p->d_ri, nullptr, nullptr, stream);
+    } else {
+      std::vector<const void*> host_ptrs(2 * (size_t)k);
+      for (int i = 0; i < k; ++i) {
+        host_ptrs[i] = colptr[i];
+        host_ptrs[k + i] = rowidx[i];
+      }
+      launch_put_ptrs(host_ptrs.data(), 2 * k, (const void**)p->d_cp, p->d_sum, p->d_dummy, stream);
+    }
   }
   if (o.flags & SPKADD_FLAG_VALIDATE) {
     TraceScope t(p, "validate", stream);
@@ -1020,6 +1035,36 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
     if ((st = check_lds(p))) return fail(st);
     if ((st = (p->unsorted_in ? build_windows_unsorted(p, stream) : build_windows(p, stream)))) return fail(st);
     if ((st = check_device_err(p))) return fail(st);
+  }
+  return SPKADD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void spkadd_opts_default(spkadd_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->force_bin = SPKADD_BIN_AUTO;
+}
+
+const char* spkadd_last_error(void) { return g_last_error.c_str(); }
+
+spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, const int32_t* const* colptr,
+                          const int32_t* const* rowidx, spkadd_dtype dtype, const spkadd_opts* opts,
+                          hipStream_t stream) {
+  g_last_error.clear();
+  if (!out) return set_error(SPKADD_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  auto* p = new (std::nothrow) spkadd_plan_s();
+  if (!p) return set_error(SPKADD_ERR_OOM, "host allocation failed");
+  const spkadd_status st = plan_build(p, m, n, k, colptr, rowidx, dtype, opts, stream);
+  if (st != SPKADD_OK) {
+    release_all(p);
+    clear_trace(p);
+    delete p;
+    return st;
   }
   *out = p;
   return SPKADD_OK;
@@ -1178,3 +1223,37 @@ spkadd_status spkadd_trace_reset(spkadd_plan_t p) {
 }
 
 }  // extern "C"
+
+namespace spk {
+
+spkadd_status sum_in_region(void* region, size_t region_bytes, int32_t m, int32_t n, int32_t k,
+                            const int32_t* const* colptr, const int32_t* const* rowidx, const void* const* values,
+                            spkadd_dtype dtype, const spkadd_opts* opts, int32_t* colptr_c, int32_t* rowidx_c,
+                            void* values_c, int64_t cap_c, int64_t* nnz_c, hipStream_t stream) {
+  g_last_error.clear();
+  if (!nnz_c || !colptr_c || !values) return set_error(SPKADD_ERR_INVALID, "NULL argument");
+  *nnz_c = -1;
+  if (cap_c < 0) return set_error(SPKADD_ERR_INVALID, "cap_c must be >= 0");
+  spkadd_opts o;
+  spkadd_opts_default(&o);
+  if (opts) o = *opts;
+  o.flags &= ~(SPKADD_FLAG_TRACE | SPKADD_FLAG_TRACE_NUMERIC);  // (traces take events)
+  spkadd_plan_s p;
+  p.region_mode = true;
+  p.region = (char*)region;
+  p.region_bytes = region_bytes;
+  spkadd_status st = plan_build(&p, m, n, k, colptr, rowidx, dtype, &o, stream);
+  int64_t nnz = -1;
+  if (st == SPKADD_OK) st = spkadd_symbolic(&p, colptr_c, &nnz, stream);
+  if (st == SPKADD_OK) {
+    *nnz_c = nnz;
+    if (nnz > cap_c)
+      st = set_error(SPKADD_ERR_INVALID, "nnz(B) = %lld exceeds cap_c = %lld (colptr_c and *nnz_c are written)",
+                     (long long)nnz, (long long)cap_c);
+  }
+  if (st == SPKADD_OK) st = spkadd_numeric(&p, values, rowidx_c, values_c, stream);
+  release_all(&p);
+  return st;
+}
+
+}  // namespace spk
