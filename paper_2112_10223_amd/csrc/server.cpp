@@ -192,9 +192,13 @@ bool admit(spkadd_server_s* s, Lane& ln) {
     s->pending.pop_front();
   }
   if (ids.empty()) return false;
-  spkadd_batch_t b = ln.batch[ln.next];
-  ln.next ^= 1;
+  // the lane's batch object that no run in flight uses (depth <= 2, two objects)
+  int slot = ln.next;
+  for (const InFlight& f : ln.inflight)
+    if (f.batch == ln.batch[slot]) slot ^= 1;
+  spkadd_batch_t b = ln.batch[slot];
   const spkadd_status st = spkadd_batch_run(b, reqs.data(), (int32_t)reqs.size(), 1, ln.stream);
+  if (st == SPKADD_OK) ln.next = slot ^ 1;  // a failed run leaves the object free for the next
   if (st != SPKADD_OK) {
     for (uint64_t id : ids) complete(s, s->tickets[id], -(int)st, -1, 0);
     s->cv_done.notify_all();
@@ -306,7 +310,7 @@ spkadd_status spkadd_server_create(spkadd_server_t* out, const spkadd_server_con
   *out = nullptr;
   if (cfg->dtype != SPKADD_F32 && cfg->dtype != SPKADD_F64) return sfail(SPKADD_ERR_INVALID, "bad dtype");
   if (cfg->n_streams < 1 || cfg->n_streams > 8) return sfail(SPKADD_ERR_INVALID, "n_streams must be 1..8");
-  if (cfg->max_batch < 1 || cfg->max_batch > 4096) return sfail(SPKADD_ERR_INVALID, "max_batch must be 1..4096");
+  if (cfg->max_batch < 0 || cfg->max_batch > 4096) return sfail(SPKADD_ERR_INVALID, "max_batch must be 0..4096");
   if (cfg->depth < 1 || cfg->depth > 2) return sfail(SPKADD_ERR_INVALID, "depth must be 1 or 2");
   if (cfg->max_columns < 1 || cfg->max_inputs < 1 || cfg->hbm_budget == 0)
     return sfail(SPKADD_ERR_INVALID, "max_columns, max_inputs and hbm_budget must be positive");
@@ -316,6 +320,8 @@ spkadd_status spkadd_server_create(spkadd_server_t* out, const spkadd_server_con
   spkadd_opts_default(&s->opts);
   if (cfg->opts) s->opts = *cfg->opts;
   s->cfg.opts = nullptr;
+  if (s->cfg.max_batch == 0)  // the tuned run size, else 8
+    s->cfg.max_batch = s->opts.batch_run_size > 0 && s->opts.batch_run_size <= 4096 ? s->opts.batch_run_size : 8;
   s->vbytes = cfg->dtype == SPKADD_F64 ? 8 : 4;
   s->t0 = std::chrono::steady_clock::now();
   if (hipGetDevice(&s->device) != hipSuccess) {
@@ -338,7 +344,7 @@ spkadd_status spkadd_server_create(spkadd_server_t* out, const spkadd_server_con
     if (hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) != hipSuccess) return cleanup(SPKADD_ERR_HIP, "stream");
     for (auto& b : ln.batch) {
       const spkadd_status st =
-          spkadd_batch_create(&b, cfg->dtype, cfg->max_batch, cfg->max_columns, cfg->max_inputs, &s->opts);
+          spkadd_batch_create(&b, cfg->dtype, s->cfg.max_batch, cfg->max_columns, cfg->max_inputs, &s->opts);
       if (st != SPKADD_OK) return cleanup(st, "batch creation failed");
     }
   }

@@ -15,7 +15,12 @@ class StreamingSum:
 
     add(colptrs, rowidxs, values) takes one batch (k-lists of device tensors, as
     binding.spkadd); result() returns (colptr, rowidx, values) of the sum so far, or
-    None before the first batch."""
+    None before the first batch.
+
+    The sums run on `stream` (torch's current stream when None); each new sum's
+    outputs are allocated on that stream (binding.spkadd), so dropping the previous
+    running sum cannot release its memory to other streams while the new sum still
+    reads it."""
 
     def __init__(self, m: int, n: int, opts=None, stream=None):
         self.m, self.n = m, n

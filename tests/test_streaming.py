@@ -54,3 +54,26 @@ def test_streaming_windows():
     torch.cuda.synchronize()
     assert_matches(b, (c.cpu().numpy().astype(np.int64), r.cpu().numpy(), v.cpu().numpy()), oracle.spkadd(b),
                    exact_values=True)
+
+
+def test_streaming_on_a_side_stream():
+    """Sums on a stream other than torch's current one, with other work allocating on
+    the current stream between batches: every running sum dropped while the next sum
+    still reads it keeps its memory until that stream has passed it."""
+    import torch
+    from paper_2112_10223_amd.streaming import StreamingSum
+    note("streaming side stream")
+    b = workloads.er(20000, 2000, 12, 40.0, seed=502, values="int32f")
+    cps, ris, vas = to_device(b)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    s = StreamingSum(b.m, b.n, stream=side)
+    junk = []
+    for at in range(0, 12, 3):
+        s.add(cps[at:at + 3], ris[at:at + 3], vas[at:at + 3])
+        junk.append(torch.full((1 << 20,), 7, dtype=torch.int32, device="cuda:0"))  # current-stream allocations
+    c, r, v = s.result()
+    side.synchronize()
+    torch.cuda.synchronize()
+    assert_matches(b, (c.cpu().numpy().astype(np.int64), r.cpu().numpy(), v.cpu().numpy()), oracle.spkadd(b),
+                   exact_values=True)
