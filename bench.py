@@ -75,9 +75,22 @@ def kernel_of_column(u: np.ndarray, cap: int, wave_max: int = 1024, merge: bool 
     return names
 
 
-def source_sha() -> str:
+# kernel sources whose change makes a committed traffic summary stale, by trace-name prefix
+_KERNEL_SOURCES = {
+    "num_wave": ("hash_kernels.hip", "wave_kernels.hip", "wave_device.h", "hash_common.h", "device.h", "internal.h"),
+    "num_window": ("bitmap_wg.hip", "bitmap_wg_device.h", "hash_kernels.hip", "hash_common.h", "device.h",
+                   "internal.h"),
+}
+
+
+def source_sha(kernel: str = "num_wave") -> str:
+    """Hash of the sources the kernel (by trace name) is compiled from."""
+    files = next((v for key, v in _KERNEL_SOURCES.items() if kernel.startswith(key)), None)
+    if files is None:
+        files = tuple(sorted(f for f in os.listdir(os.path.join(ROOT, "paper_2112_10223_amd", "csrc"))
+                             if f.endswith((".hip", ".h"))))
     h = hashlib.sha256()
-    for fn in ("hash_kernels.hip", "wave_kernels.hip", "wave_device.h", "hash_common.h", "device.h", "internal.h"):
+    for fn in files:
         with open(os.path.join(ROOT, "paper_2112_10223_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -92,7 +105,7 @@ def measured_traffic(kernel: str, workload: str):
     if not os.path.exists(path):
         return None
     rec = profiling.read_traffic_summary(path)
-    if rec.get("source_sha") != source_sha():
+    if rec.get("source_sha") != source_sha(kernel):
         return None
     return int(rec["traffic_bytes_per_launch"])
 
@@ -345,7 +358,7 @@ def cpu_baseline_all_cores(batch):
     the oracle's C routine runs without the interpreter lock)."""
     import concurrent.futures as cf
     import oracle
-    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    threads = max(1, len(os.sched_getaffinity(0)))
     chunks = np.array_split(np.arange(batch.n, dtype=np.int64), threads * 4)
     oracle.spkadd(batch, cols=chunks[0][:1])  # library loaded before timing
     t0 = time.perf_counter()
@@ -413,44 +426,30 @@ def reversed_columns(batch):
     return workloads.CSCBatch(batch.m, batch.n, batch.colptr, rows, vals)
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--no-trace", action="store_true", help="time without per-kernel events")
-    ap.add_argument("--trace-steps", type=int, default=3, help="untimed steps with every launch traced")
-    ap.add_argument("--tune", action="store_true", help="autotune the launch parameters on the workload first")
-    ap.add_argument("--unsorted-in", action="store_true",
-                    help="every input column reversed (descending rows), planned with SPKADD_FLAG_UNSORTED_IN")
-    ap.add_argument("--unsorted-out", action="store_true",
-                    help="rows of each output column in any order (hash accumulators skip their sort)")
-    ap.add_argument("--no-compare", action="store_true",
-                    help="skip the comparison with the heap-merge and 2-way-tree baselines")
-    ap.add_argument("--batched", type=int, default=400,
-                    help="requests of the batched-vs-plain measurement (0 = skip)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the SpKAdd path here is single-GPU.",
-              file=sys.stderr)
-        return 2
+def host_cpu() -> dict:
+    """The host the CPU baseline runs on: cores in this process's affinity mask,
+    all online cores, and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"affinity_cores": len(os.sched_getaffinity(0)), "nproc": os.cpu_count(), "model": model}
 
+
+def measure_workload(name: str, batch, steps: int, warmup: int, trace_steps: int, trace: bool = True,
+                     flags: int = 0, tune: bool = False) -> dict:
+    """Times `steps` steps (plan + symbolic + numeric on resident inputs, outputs
+    preallocated) of one workload after `warmup` untimed ones; the numeric launches of
+    the timed steps carry HIP events (SPKADD_FLAG_TRACE_NUMERIC) for the roofline of
+    the dominant kernel, and `trace_steps` more untimed steps trace every launch for
+    the phase breakdown."""
     import torch
-    if args.copy_calibration:
-        copy_calibration()
-        return 0
     from paper_2112_10223_amd import binding
-    if not os.path.exists(binding.LIB_PATH):
-        import __graft_entry__
-        __graft_entry__.build()
-
-    desc, make = WORKLOADS[args.workload]
-    batch = make()
-    if args.unsorted_in:
-        batch = reversed_columns(batch)
     k, m, n = batch.k, batch.m, batch.n
     f64 = batch.vals[0].dtype == np.float64
     vbytes = 8 if f64 else 4
@@ -459,14 +458,10 @@ def main() -> int:
     ris = [torch.from_numpy(r).to(dev) for r in batch.rowidx]
     vas = [torch.from_numpy(v).to(dev) for v in batch.vals]
     dtype = binding.SPKADD_F64 if f64 else binding.SPKADD_F32
-    # timed steps record HIP events around the numeric launches only (the dominant
-    # kernels); a separate untimed pass traces every launch for the phase breakdown
-    order = (binding.SPKADD_FLAG_UNSORTED_OUT if args.unsorted_out else 0) | \
-        (binding.SPKADD_FLAG_UNSORTED_IN if args.unsorted_in else 0)
-    opts = binding.make_opts(flags=order | (0 if args.no_trace else binding.SPKADD_FLAG_TRACE_NUMERIC))
-    opts_all = binding.make_opts(flags=order | binding.SPKADD_FLAG_TRACE)
+    opts = binding.make_opts(flags=flags | (binding.SPKADD_FLAG_TRACE_NUMERIC if trace else 0))
+    opts_all = binding.make_opts(flags=flags | binding.SPKADD_FLAG_TRACE)
     tuned = None
-    if args.tune:  # the autotuner on this workload; the timed steps then use its choice
+    if tune:  # the autotuner on this workload; the timed steps then use its choice
         best, rep, trials = binding.tune(m, cps, ris, vas, dtype, reps=5)
         for o in (opts, opts_all):
             for f in binding.TUNED_FIELDS:
@@ -491,13 +486,12 @@ def main() -> int:
     # runs the whole path on the device
     pcp, pri, pva = binding.PtrArray(cps), binding.PtrArray(ris), binding.PtrArray(vas, non_null=True)
     stream = binding._stream_ptr(None)
-
     host_s = {"plan": 0.0, "symbolic": 0.0, "numeric": 0.0}
-
-    step_events = []  # (end of the previous step, end of this one) on the launch stream
+    step_events = []  # (start, end) of each timed step on the launch stream
+    collect_steps = [False]
 
     def step(o):
-        if step_events is not None and collect_steps[0]:
+        if collect_steps[0]:
             ev = torch.cuda.Event(enable_timing=True)
             ev.record()
             step_events.append(ev)
@@ -517,8 +511,6 @@ def main() -> int:
             step_events.append(ev)
         return p
 
-    collect_steps = [False]
-
     def run(nsteps, o, collect):
         """nsteps steps; a plan is freed (after reading its trace) once the next one is
         queued, so no step waits for the previous one to drain."""
@@ -532,7 +524,7 @@ def main() -> int:
             prev = p
         return prev, traces
 
-    last, _ = run(args.warmup, opts, False)
+    last, _ = run(warmup, opts, False)
     if last is not None:
         last.free()
     torch.cuda.synchronize()
@@ -540,30 +532,27 @@ def main() -> int:
         host_s[kk] = 0.0
     collect_steps[0] = True
     t0 = time.perf_counter()
-    last, traces = run(args.steps, opts, not args.no_trace)
+    last, traces = run(steps, opts, trace)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     collect_steps[0] = False
-    # per-step device time: from the end of the previous step's launches to the end of
-    # this step's on the stream (a step starts when the device reaches its first launch)
     step_ms = [step_events[2 * i].elapsed_time(step_events[2 * i + 1]) for i in range(len(step_events) // 2)]
     step_ms_q = {f"p{q}": round(float(np.percentile(step_ms, q)), 4) for q in (10, 50, 90)} if step_ms else None
-    if not args.no_trace:
+    if trace:
         traces.append(binding.spkadd_trace(last))
     last.free()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    host_call_ms = {kk: round(v * 1e3 / args.steps, 4) for kk, v in host_s.items()}
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    host_call_ms = {kk: round(v * 1e3 / steps, 4) for kk, v in host_s.items()}
 
     def mean_by_kernel(trs):
         per = {}
         for tr in trs:
-            for name, ms in tr:
-                per.setdefault(name, []).append(ms)
+            for kname, ms in tr:
+                per.setdefault(kname, []).append(ms)
         return {kname: float(np.mean(v)) for kname, v in per.items()}
 
     mean_ms = mean_by_kernel(traces)  # numeric launches of the timed steps
-    # phase breakdown: a few more steps with every launch traced (not timed)
-    last, tr_all = run(args.trace_steps, opts_all, True)
+    last, tr_all = run(trace_steps, opts_all, True)
     if last is not None:
         tr_all.append(binding.spkadd_trace(last))
         last.free()
@@ -571,7 +560,7 @@ def main() -> int:
     all_ms = mean_by_kernel(tr_all)
     phase_ms = {"plan": 0.0, "symbolic": 0.0, "numeric": 0.0}
     for kname, ms in all_ms.items():
-        ph = "numeric" if kname.startswith(("num_", "put_ptrs_num")) else \
+        ph = "numeric" if kname.startswith(("num_", "put_ptrs_num", "uwin_gather")) else \
             "symbolic" if kname.startswith(("sym_", "scan", "win_colsum")) else "plan"
         phase_ms[ph] += ms
 
@@ -583,10 +572,10 @@ def main() -> int:
     cap = stats["window_cap"]
     kern = kernel_of_column(u, cap)
     roofline = None
-    num_kernels = [kname for kname in mean_ms if kname.startswith("num_")]
+    num_kernels = [kname for kname in mean_ms if kname.startswith("num_") and kname != "num_ordered"]
     if not num_kernels:  # timed without events: fall back to the traced pass
         mean_ms = all_ms
-        num_kernels = [kname for kname in mean_ms if kname.startswith("num_")]
+        num_kernels = [kname for kname in mean_ms if kname.startswith("num_") and kname != "num_ordered"]
     if num_kernels:
         dom = max(num_kernels, key=lambda x: mean_ms[x])
         sel = kern == dom
@@ -594,51 +583,142 @@ def main() -> int:
         achieved = alg_bytes / (mean_ms[dom] * 1e-3) / 1e9
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                    "traffic": measured_traffic(dom, args.workload),
+                    "traffic": measured_traffic(dom, name),
                     "alg_bytes_per_launch": alg_bytes, "mean_launch_ms": round(mean_ms[dom], 5),
                     "units_per_launch": int(sel.sum())}
 
     b_alg = (8 + vbytes) * nnz_in + (4 + vbytes) * nnz_out + 12 * k * (n + 1) + 12 * (n + 1)
     b_min = (4 + vbytes) * (nnz_in + nnz_out) + 4 * (k + 1) * (n + 1)  # every byte read or written once
-    value = nnz_in / (ms_per_step * 1e-3)
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "input nnz/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+    rec = {
         "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
+        "steps": steps,
+        "warmup": warmup,
+        "value": nnz_in / (ms_per_step * 1e-3),
+        "unit": "input nnz/s",
         "dtype": "f64" if f64 else "f32",
-        "data": "synthetic (seeded generator; paper's R-MAT family, no public datasets)",
-        "config": {"workload": f"{args.workload}: {desc}", "k": k, "m": m, "n": n, "nnz_in": nnz_in,
-                   "nnz_out": nnz_out, "parallelism": "single GPU",
-                   "output_order": "any" if args.unsorted_out else "sorted",
-                   "input_order": "descending (reversed columns)" if args.unsorted_in else "ascending"},
+        "k": k, "m": m, "n": n, "nnz_in": nnz_in, "nnz_out": nnz_out,
         "hbm_gbps_alg_step": round(b_alg / (ms_per_step * 1e-3) / 1e9, 1),
         "hbm_frac_alg_step": round(b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "hbm_gbps_min_step": round(b_min / (ms_per_step * 1e-3) / 1e9, 1),
         "step_ms": step_ms_q,
-        "copy_gbps": copy_bandwidth(),
         "phase_ms": {kk: round(v, 4) for kk, v in phase_ms.items()},
         "host_call_ms": host_call_ms,
         "kernel_ms": {kk: round(v, 5) for kk, v in sorted(all_ms.items())},
         "bins": {kk: stats[kk] for kk in ("n_wave_cols", "n_wg_cols", "n_window_cols", "n_windows")},
         "roofline": roofline,
-        "cpu_baseline": None,
     }
     if tuned is not None:
-        out["tune"] = tuned
+        rec["tune"] = tuned
+    rec["_device"] = (cps, ris, vas, nnz_out)  # for the algorithm comparison (removed before printing)
+    return rec
+
+
+# the other single-GPU workloads timed beside the headline one: (name, timed steps, warm-up steps)
+SUB_WORKLOADS = [("config2_f64", 20, 3), ("config4", 5, 2), ("config3", 3, 2)]
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-trace", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--trace-steps", type=int, default=3, help="untimed steps with every launch traced")
+    ap.add_argument("--tune", action="store_true", help="autotune the launch parameters on the workload first")
+    ap.add_argument("--unsorted-in", action="store_true",
+                    help="every input column reversed (descending rows), planned with SPKADD_FLAG_UNSORTED_IN")
+    ap.add_argument("--unsorted-out", action="store_true",
+                    help="rows of each output column in any order (hash accumulators skip their sort)")
+    ap.add_argument("--ordered", action="store_true", help="values summed in input order (SPKADD_FLAG_ORDERED)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the comparison with the heap-merge and 2-way-tree baselines")
+    ap.add_argument("--batched", type=int, default=400,
+                    help="requests of the batched-vs-plain measurement (0 = skip)")
+    ap.add_argument("--no-sub", action="store_true",
+                    help="time only --workload (not also the fp64, tall-skinny and R-MAT workloads)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the SpKAdd path here is single-GPU.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    if args.copy_calibration:
+        copy_calibration()
+        return 0
+    from paper_2112_10223_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+
+    desc, make = WORKLOADS[args.workload]
+    batch = make()
+    if args.unsorted_in:
+        batch = reversed_columns(batch)
+    flags = (binding.SPKADD_FLAG_UNSORTED_OUT if args.unsorted_out else 0) | \
+        (binding.SPKADD_FLAG_UNSORTED_IN if args.unsorted_in else 0) | \
+        (binding.SPKADD_FLAG_ORDERED if args.ordered else 0)
+    head = measure_workload(args.workload, batch, args.steps, args.warmup, args.trace_steps, not args.no_trace,
+                            flags, args.tune)
+    cps, ris, vas, nnz_out = head.pop("_device")
+    k, m, n = batch.k, batch.m, batch.n
+    out = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "input nnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head["dtype"],
+        "data": "synthetic (seeded generator; paper's R-MAT family, no public datasets)",
+        "config": {"workload": f"{args.workload}: {desc}", "k": k, "m": m, "n": n, "nnz_in": batch.nnz_in,
+                   "nnz_out": nnz_out, "parallelism": "single GPU",
+                   "output_order": "any" if args.unsorted_out else "sorted",
+                   "input_order": "descending (reversed columns)" if args.unsorted_in else "ascending",
+                   "summation": "input order" if args.ordered else "any order"},
+    }
+    for key in ("hbm_gbps_alg_step", "hbm_frac_alg_step", "hbm_gbps_min_step", "step_ms"):
+        out[key] = head[key]
+    out["copy_gbps"] = copy_bandwidth()
+    for key in ("phase_ms", "host_call_ms", "kernel_ms", "bins", "roofline"):
+        out[key] = head[key]
+    out["cpu_baseline"] = None
+    if "tune" in head:
+        out["tune"] = head["tune"]
     if not args.no_compare and not args.unsorted_in and k <= 128:
-        out["algorithms"] = compare_algorithms(m, cps, ris, vas, nnz_out, ms_per_step)
-    if args.batched > 0:
-        out["served"], out["batched"] = measure_batched(args.batched)
+        out["algorithms"] = compare_algorithms(m, cps, ris, vas, nnz_out, head["ms_per_step"])
     if not args.no_cpu_baseline:
+        out["cpu_host"] = host_cpu()
         out["cpu_baseline"] = cpu_baseline(batch)
         out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(batch)
+    del cps, ris, vas, batch
+    torch.cuda.empty_cache()
+    if args.batched > 0:
+        out["served"], out["batched"] = measure_batched(args.batched)
+        torch.cuda.empty_cache()
+    if not args.no_sub and not (args.unsorted_in or args.unsorted_out or args.ordered or args.tune):
+        subs = {}
+        for wname, wsteps, wwarm in SUB_WORKLOADS:
+            if wname == args.workload:
+                continue
+            wdesc, wmake = WORKLOADS[wname]
+            wb = wmake()
+            rec = measure_workload(wname, wb, wsteps, wwarm, 1)
+            rec.pop("_device")
+            rec["workload"] = f"{wname}: {wdesc}"
+            for key in ("host_call_ms", "kernel_ms", "step_ms"):
+                rec.pop(key, None)
+            subs[wname] = rec
+            del wb
+            torch.cuda.empty_cache()
+        out["workloads"] = subs
     print(json.dumps(out))
     return 0
 
