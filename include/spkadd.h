@@ -121,6 +121,15 @@ typedef struct spkadd_opts {
                               columns in total does each pass in one launch over every wave
                               bin; larger runs launch one kernel per bin and accumulator.
                               0 = default (no limit: every run), negative = never */
+  int32_t batch_wave_max;   /* batched runs: a column with u_j up to this goes one wavefront per
+                              column (64..1024; 0 = 1024) */
+  int32_t batch_wg_max;     /* batched runs: longer columns with up to this many entries go one
+                              workgroup per column (requests of at most 2^17 rows); longer ones
+                              make the request SPKADD_REQ_TOO_LARGE (batch_wave_max..4096;
+                              0 = 4096) */
+  int32_t batch_wg_threads; /* batched runs: threads of those workgroups, 256 or 512 (0 = 256) */
+  int32_t batch_run_size;   /* requests per batched run found fastest by spkadd_tune_batch; the
+                              serving loop uses it when its config's max_batch is 0 (0 = none) */
 } spkadd_opts;
 
 typedef struct spkadd_plan_s* spkadd_plan_t;

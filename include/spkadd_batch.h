@@ -17,10 +17,13 @@
  * always suffices (nnz(B) never exceeds it).  The host learns nnz(B_r) only from
  * spkadd_batch_results, after the run.
  *
- * Limits: k_r <= 64, and every column of a request must have at most 1024 input
- * entries (u_j <= 1024); a request with a longer column is reported as
- * SPKADD_REQ_TOO_LARGE and left for the one-request path (spkadd_plan /
- * spkadd_symbolic / spkadd_numeric).
+ * Limits: k_r <= 64.  A column with u_j up to opts.batch_wave_max (1024 by default)
+ * runs one wavefront per column; a longer one, up to opts.batch_wg_max (4096 by
+ * default), one workgroup per column if its request has at most 2^17 rows.  A
+ * request with a longer column is reported as SPKADD_REQ_TOO_LARGE and left for the
+ * one-request path (spkadd_plan / spkadd_symbolic / spkadd_numeric).  These cutoffs,
+ * the workgroup size, the accumulator choice, the fused launch and the run size are
+ * what spkadd_tune_batch (spkadd_tune.h) measures.
  *
  * Memory: requests are HOST structs holding DEVICE pointers (all non-NULL, also for
  * inputs without entries); the batch copies them at run time.  Inputs and outputs
@@ -51,7 +54,9 @@ typedef struct spkadd_request {
 
 /* per-request outcome (spkadd_batch_results) */
 #define SPKADD_REQ_OK 0
-#define SPKADD_REQ_TOO_LARGE 1 /* some column has more than 1024 input entries: nothing written */
+#define SPKADD_REQ_TOO_LARGE 1 /* some column has more input entries than a batched run takes
+                                  (opts.batch_wg_max, 4096 by default; opts.batch_wave_max, 1024,
+                                  in requests of more than 2^17 rows): nothing written */
 #define SPKADD_REQ_CAPACITY 2  /* nnz(B) > cap_c: colptr(B) written, rows and values not */
 
 typedef struct spkadd_batch_s* spkadd_batch_t;

@@ -6,7 +6,8 @@
  * memory fits the HBM budget and a stream has room for another run (config depth),
  * groups them into batched runs (include/spkadd_batch.h) over one or more streams,
  * and completes the tickets.  A request that a batch reports as too large
- * for a wavefront (a column with more than 1024 input entries) goes through the
+ * (a column with more entries than opts.batch_wg_max, 4096 by default, or than
+ * opts.batch_wave_max in a request of more than 2^17 rows) goes through the
  * one-request path (spkadd_plan / spkadd_symbolic / spkadd_numeric) on a stream of its
  * own.  Requests that arrive while others are on the device join the next run.
  *
@@ -34,7 +35,8 @@ typedef struct spkadd_server_s* spkadd_server_t;
 typedef struct spkadd_server_config {
   spkadd_dtype dtype;
   int32_t n_streams;       /* streams that batched runs rotate over (1..8) */
-  int32_t max_batch;       /* requests per batched run (1..4096) */
+  int32_t max_batch;       /* requests per batched run (1..4096); 0 = opts->batch_run_size
+                              (the run size spkadd_tune_batch found fastest) if set, else 8 */
   int32_t depth;           /* runs in flight per stream (1 or 2): with 1, requests that
                               arrive while a stream's run executes wait and join its
                               next run (larger runs); with 2, the next run is enqueued

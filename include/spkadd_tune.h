@@ -26,13 +26,15 @@
 #define SPKADD_TUNE_H
 
 #include "spkadd.h"
+#include "spkadd_batch.h"
 
 #ifdef __cplusplus
 extern "C" {
 #endif
 
 /* Shape class of an SpKAdd: the device, the value type and the orders of magnitude
- * of m, n, k and of the mean input entries per column. */
+ * of m, n, k and of the mean input entries per column; kind tells one SpKAdd from a
+ * set of batched requests. */
 typedef struct spkadd_tune_key {
   char arch[64];   /* device architecture name (hipDeviceProp_t.gcnArchName) */
   int32_t cus;     /* compute units */
@@ -41,6 +43,8 @@ typedef struct spkadd_tune_key {
   int32_t n_log2;
   int32_t k_log2;
   int32_t u_log2;  /* ceil(log2(nnz_in / n)) (0 for n == 0 or nnz_in <= n) */
+  int32_t kind;    /* 0: one SpKAdd (spkadd_tune); 1: a set of batched requests
+                      (spkadd_tune_batch), m, n, k and u then their means */
 } spkadd_tune_key;
 
 /* The key of an SpKAdd on the current device.  Errors: INVALID, HIP. */
@@ -79,6 +83,34 @@ spkadd_status spkadd_tune(int32_t m, int32_t n, int32_t k, const int32_t* const*
                           const void* const* values, spkadd_dtype dtype, const spkadd_opts* base, int32_t reps,
                           spkadd_opts* best, spkadd_tune_report* report, spkadd_tune_trial* trials,
                           int32_t max_trials, hipStream_t stream);
+
+/* The key (kind 1) of a set of batched requests on the current device: nreq requests
+ * whose m, n and k add up to sum_m, sum_n, sum_k, with nnz_in input entries in all.
+ * Errors: INVALID, HIP. */
+spkadd_status spkadd_tune_key_for_batch(int32_t nreq, int64_t sum_m, int64_t sum_n, int64_t sum_k, int64_t nnz_in,
+                                        spkadd_dtype dtype, spkadd_tune_key* out);
+
+/*
+ * spkadd_tune_batch -- the batched path's counterpart of spkadd_tune: measures
+ * settings of the batched runs (spkadd_batch.h) on a sample of requests and keeps the
+ * fastest under the sample's key (kind 1).  Searched, one parameter at a time from
+ * *base: the requests per run (batch_run_size: 8, 16, 32, 64), the wavefront and
+ * workgroup cutoffs (batch_wave_max: 1024, 768, 512; batch_wg_max: 4096, 3072, 2048),
+ * the wavefront accumulator (bitmap_ratio 1, 0.5, 2, 4, or hash tables), one fused
+ * launch per pass or one per slot (batch_fused_cols 0 / -1) and the workgroup size
+ * (batch_wg_threads 256 / 512).  A trial runs every request: runs of batch_run_size
+ * requests through two batch objects that alternate (graphs captured in an untimed
+ * first pass), then the requests a run reports too large through the one-request
+ * path, as the serving loop does; its time is the median of `reps` passes, and
+ * nnz(B_r) of every request must equal the first trial's.
+ *   reqs, nreq : the sample (as spkadd_batch_run; outputs are written by every trial).
+ *   best       : receives *base with the tuned fields (batch_run_size included).
+ * Errors: INVALID, OOM, HIP, or the status of the starting setting if it fails.
+ */
+spkadd_status spkadd_tune_batch(const spkadd_request* reqs, int32_t nreq, spkadd_dtype dtype,
+                                const spkadd_opts* base, int32_t reps, spkadd_opts* best,
+                                spkadd_tune_report* report, spkadd_tune_trial* trials, int32_t max_trials,
+                                hipStream_t stream);
 
 /* Applies the cached setting of *key to *inout (the tuned fields only; flags and test
  * hooks stay).  *found = 1 if there was one, 0 otherwise (then *inout is unchanged).

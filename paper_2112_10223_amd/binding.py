@@ -36,7 +36,9 @@ class Opts(ctypes.Structure):
                 ("hash_mode", ctypes.c_int32), ("wave_max", ctypes.c_int32), ("load_factor_sym", ctypes.c_float),
                 ("load_factor_num", ctypes.c_float), ("window_fill", ctypes.c_float),
                 ("accum_mode", ctypes.c_int32), ("bitmap_ratio", ctypes.c_float), ("wave_merge", ctypes.c_int32),
-                ("batch_fused_cols", ctypes.c_int32)]
+                ("batch_fused_cols", ctypes.c_int32), ("batch_wave_max", ctypes.c_int32),
+                ("batch_wg_max", ctypes.c_int32), ("batch_wg_threads", ctypes.c_int32),
+                ("batch_run_size", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -243,16 +245,27 @@ def spkadd(m, colptrs, rowidxs, values, opts: Opts | None = None, stream=None):
 
     Inputs are k-lists of device tensors (int32 colptr[n+1], int32 rowidx, float32 or
     float64 values).  Returns (colptr, rowidx, values) of B as device tensors."""
+    import contextlib
     import torch
     n = colptrs[0].shape[0] - 1
     dtype = SPKADD_F64 if values[0].dtype == torch.float64 else SPKADD_F32
     dev = colptrs[0].device
+    # the outputs are allocated on the stream the work runs on, so that torch's caching
+    # allocator does not hand their memory (or, once they are dropped, that of a
+    # running sum fed back as an input) to other work before this stream reaches it
+    ctx = contextlib.nullcontext()
+    if stream is not None and not isinstance(stream, torch.cuda.Stream):
+        raw = stream.value if isinstance(stream, ctypes.c_void_p) else int(stream)
+        stream = torch.cuda.ExternalStream(raw, device=dev) if raw else None
+    if stream is not None and stream != torch.cuda.current_stream(dev):
+        ctx = torch.cuda.stream(stream)
     plan = spkadd_plan(m, n, colptrs, rowidxs, dtype, opts, stream)
     try:
-        colptr_c = torch.empty(n + 1, dtype=torch.int32, device=dev)
-        nnz = spkadd_symbolic(plan, colptr_c, stream)
-        rowidx_c = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)[:nnz]
-        values_c = torch.empty(max(nnz, 1), dtype=values[0].dtype, device=dev)[:nnz]
+        with ctx:
+            colptr_c = torch.empty(n + 1, dtype=torch.int32, device=dev)
+            nnz = spkadd_symbolic(plan, colptr_c, stream)
+            rowidx_c = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)[:nnz]
+            values_c = torch.empty(max(nnz, 1), dtype=values[0].dtype, device=dev)[:nnz]
         spkadd_numeric(plan, values, rowidx_c, values_c, stream)
     finally:
         plan.free()
@@ -286,6 +299,27 @@ def spkadd_sum_noalloc(m, colptrs, rowidxs, values, colptr_c, rowidx_c, values_c
     return int(nnz.value)
 
 
+def request_array(requests):
+    """(ctypes array of spkadd_request, objects to keep alive) from request dicts: m,
+    colptrs, rowidxs, values (k device tensors or PtrArray each), colptr_c, rowidx_c,
+    values_c (device tensors) and cap_c."""
+    arr = (Request * len(requests))()
+    keep = []
+    for r, q in enumerate(requests):
+        # inputs without entries still need a device pointer (never read through)
+        fb = q["colptr_c"].data_ptr()
+        cps = q["colptrs"] if isinstance(q["colptrs"], PtrArray) else PtrArray(q["colptrs"], True, fb)
+        ris = q["rowidxs"] if isinstance(q["rowidxs"], PtrArray) else PtrArray(q["rowidxs"], True, fb)
+        vas = q["values"] if isinstance(q["values"], PtrArray) else PtrArray(q["values"], True, fb)
+        keep += [cps, ris, vas, q["colptr_c"], q["rowidx_c"], q["values_c"]]
+        n = q["colptr_c"].shape[0] - 1
+        arr[r] = Request(q["m"], n, len(cps), ctypes.cast(cps.arr, ctypes.c_void_p).value,
+                         ctypes.cast(ris.arr, ctypes.c_void_p).value, ctypes.cast(vas.arr, ctypes.c_void_p).value,
+                         q["colptr_c"].data_ptr(), q["rowidx_c"].data_ptr() or None,
+                         q["values_c"].data_ptr() or None, int(q["cap_c"]))
+    return arr, keep
+
+
 class Batch:
     """Owning handle of an spkadd_batch_t (include/spkadd_batch.h).
 
@@ -302,20 +336,7 @@ class Batch:
         self.nreq = 0
 
     def run(self, requests, use_graph: bool = True, stream=None) -> None:
-        arr = (Request * len(requests))()
-        keep = []
-        for r, q in enumerate(requests):
-            # inputs without entries still need a device pointer (never read through)
-            fb = q["colptr_c"].data_ptr()
-            cps = q["colptrs"] if isinstance(q["colptrs"], PtrArray) else PtrArray(q["colptrs"], True, fb)
-            ris = q["rowidxs"] if isinstance(q["rowidxs"], PtrArray) else PtrArray(q["rowidxs"], True, fb)
-            vas = q["values"] if isinstance(q["values"], PtrArray) else PtrArray(q["values"], True, fb)
-            keep += [cps, ris, vas, q["colptr_c"], q["rowidx_c"], q["values_c"]]
-            n = q["colptr_c"].shape[0] - 1
-            arr[r] = Request(q["m"], n, len(cps), ctypes.cast(cps.arr, ctypes.c_void_p).value,
-                             ctypes.cast(ris.arr, ctypes.c_void_p).value, ctypes.cast(vas.arr, ctypes.c_void_p).value,
-                             q["colptr_c"].data_ptr(), q["rowidx_c"].data_ptr() or None,
-                             q["values_c"].data_ptr() or None, int(q["cap_c"]))
+        arr, keep = request_array(requests)
         _check(lib().spkadd_batch_run(self.handle, arr, len(requests), 1 if use_graph else 0, _stream_ptr(stream)))
         self._keep = keep
         self.nreq = len(requests)
@@ -493,7 +514,7 @@ class Server:
 class TuneKey(ctypes.Structure):
     _fields_ = [("arch", ctypes.c_char * 64), ("cus", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("m_log2", ctypes.c_int32), ("n_log2", ctypes.c_int32), ("k_log2", ctypes.c_int32),
-                ("u_log2", ctypes.c_int32)]
+                ("u_log2", ctypes.c_int32), ("kind", ctypes.c_int32)]
 
 
 class TuneTrial(ctypes.Structure):
@@ -507,6 +528,8 @@ class TuneReport(ctypes.Structure):
 
 TUNED_FIELDS = ("wave_max", "accum_mode", "bitmap_ratio", "wave_merge", "load_factor_sym", "load_factor_num",
                 "window_cap", "window_fill")
+BATCH_TUNED_FIELDS = ("accum_mode", "bitmap_ratio", "batch_fused_cols", "batch_wave_max", "batch_wg_max",
+                      "batch_wg_threads", "batch_run_size")
 
 
 def _tune_fns():
@@ -530,6 +553,12 @@ def _tune_fns():
         L.spkadd_tune_load.restype = ctypes.c_int
         L.spkadd_tune_clear.argtypes = []
         L.spkadd_tune_clear.restype = None
+        L.spkadd_tune_key_for_batch.argtypes = [I32, I64, I64, I64, I64, ctypes.c_int, ctypes.POINTER(TuneKey)]
+        L.spkadd_tune_key_for_batch.restype = ctypes.c_int
+        L.spkadd_tune_batch.argtypes = [ctypes.POINTER(Request), I32, ctypes.c_int, ctypes.POINTER(Opts), I32,
+                                        ctypes.POINTER(Opts), ctypes.POINTER(TuneReport), ctypes.POINTER(TuneTrial),
+                                        I32, P]
+        L.spkadd_tune_batch.restype = ctypes.c_int
         L._tune_bound = True
     return L
 
@@ -549,7 +578,35 @@ def tune_key(m, n, k, nnz_in, dtype=SPKADD_F32, arch=None, cus=None) -> TuneKey:
     def clog2(x):
         return 0 if x <= 1 else int(x - 1).bit_length()
     u = (nnz_in + n - 1) // n if n > 0 else 0
-    return TuneKey(arch.encode(), cus, dtype, clog2(m), clog2(n), clog2(k), clog2(u) if n > 0 else 0)
+    return TuneKey(arch.encode(), cus, dtype, clog2(m), clog2(n), clog2(k), clog2(u) if n > 0 else 0, 0)
+
+
+def tune_key_batch(nreq, sum_m, sum_n, sum_k, nnz_in, dtype=SPKADD_F32) -> TuneKey:
+    """The shape class (kind 1) of a set of batched requests on the current device."""
+    key = TuneKey()
+    _check(_tune_fns().spkadd_tune_key_for_batch(nreq, sum_m, sum_n, sum_k, nnz_in, dtype, ctypes.byref(key)))
+    return key
+
+
+def tune_batch(requests, dtype=SPKADD_F32, base: Opts | None = None, reps=3, stream=None, max_trials=64):
+    """Runs the batched-path tuner on a sample of requests (dicts as Batch.run takes);
+    returns (best Opts, report dict, [trial dicts])."""
+    arr, keep = request_array(requests)
+    best = Opts()
+    rep = TuneReport()
+    trials = (TuneTrial * max_trials)()
+    _check(_tune_fns().spkadd_tune_batch(arr, len(requests), dtype, ctypes.byref(base) if base is not None else None,
+                                         reps, ctypes.byref(best), ctypes.byref(rep), trials, max_trials,
+                                         _stream_ptr(stream)))
+    del keep
+    report = {"trials": rep.trials, "failed": rep.failed, "default_ms": rep.default_ms, "best_ms": rep.best_ms,
+              "key": {name: (getattr(rep.key, name).decode() if name == "arch" else getattr(rep.key, name))
+                      for name, _ in TuneKey._fields_}}
+    out = []
+    for t in trials[:min(rep.trials, max_trials)]:
+        out.append({"opts": {f: getattr(t.opts, f) for f in BATCH_TUNED_FIELDS}, "ms": t.ms, "status": t.status,
+                    "same_nnz": bool(t.same_colptr)})
+    return best, report, out
 
 
 def tune(m, colptrs, rowidxs, values, dtype=SPKADD_F32, base: Opts | None = None, reps=5, stream=None,

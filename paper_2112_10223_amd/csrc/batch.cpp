@@ -91,6 +91,7 @@ struct spkadd_batch_s {
   int last_nreq = -1;
   int graph_replays = 0;
   int kernels_per_run = 0;
+  int wg_threads = BATCH_WG_THREADS;
 };
 
 namespace {
@@ -159,9 +160,11 @@ int enqueue_wg(spkadd_batch_s* b, bool numeric, hipStream_t s) {
   a.alpha_q = 512;
   // every workgroup-slot column has at most BATCH_WG_U entries, all in registers
   lds_layout_bitmap_wg(numeric, f64 ? 8 : 4, 64, BATCH_WG_SPAN, BATCH_WG_U, BATCH_WG_U, true, 2, a);
+  // resident workgroups per CU: LDS-bound, at most 32 waves
+  const int max_blocks = 32 / (b->wg_threads / 64);
   int bpc = max_lds_bytes() / a.slice_bytes;
-  bpc = bpc < 1 ? 1 : bpc > 8 ? 8 : bpc;
-  launch_batch_wg(numeric, f64, b->args, a, (unsigned)(b->n_cu * bpc), s);
+  bpc = bpc < 1 ? 1 : bpc > max_blocks ? max_blocks : bpc;
+  launch_batch_wg(numeric, f64, b->wg_threads, b->args, a, (unsigned)(b->n_cu * bpc), s);
   return 1;
 }
 
@@ -243,6 +246,14 @@ spkadd_status spkadd_batch_create(spkadd_batch_t* out, spkadd_dtype dtype, int32
   if (!(o.bitmap_ratio >= 0.f && o.bitmap_ratio <= 64.f)) return fail(SPKADD_ERR_INVALID, "bad bitmap_ratio");
   if (o.flags & SPKADD_FLAG_ORDERED)
     return fail(SPKADD_ERR_UNSUPPORTED, "batched runs do not take SPKADD_FLAG_ORDERED (use spkadd_plan)");
+  const int wave_max = o.batch_wave_max ? o.batch_wave_max : 1024;
+  const int wg_max = o.batch_wg_max ? o.batch_wg_max : BATCH_WG_U;
+  if (wave_max < 64 || wave_max > 1024) return fail(SPKADD_ERR_INVALID, "batch_wave_max must be 0 or 64..1024");
+  if (wg_max < wave_max || wg_max > BATCH_WG_U)
+    return fail(SPKADD_ERR_INVALID, "batch_wg_max must be 0 or batch_wave_max..%d", BATCH_WG_U);
+  if (o.batch_wg_threads != 0 && o.batch_wg_threads != 256 && o.batch_wg_threads != 512)
+    return fail(SPKADD_ERR_INVALID, "batch_wg_threads must be 0, 256 or 512");
+  if (o.batch_run_size < 0) return fail(SPKADD_ERR_INVALID, "batch_run_size must be >= 0");
 
   auto* b = new (std::nothrow) spkadd_batch_s();
   if (!b) return fail(SPKADD_ERR_OOM, "host allocation failed");
@@ -312,6 +323,9 @@ spkadd_status spkadd_batch_create(spkadd_batch_t* out, spkadd_dtype dtype, int32
   a.chunk = chunk;
   a.accum_mode = o.accum_mode;
   a.bitmap_ratio = o.bitmap_ratio > 0 ? o.bitmap_ratio : 1.0f;
+  a.wave_max = wave_max;
+  a.wg_max = wg_max;
+  b->wg_threads = o.batch_wg_threads ? o.batch_wg_threads : BATCH_WG_THREADS;
   *out = b;
   return SPKADD_OK;
 }

@@ -59,10 +59,10 @@ __global__ __launch_bounds__(64 * PIPE_WAVES_PER_BLOCK) void k_batch_fused(Batch
 
 // Persistent, one launch per pass: workgroup w of W takes the columns w, w + W, ...
 // of the workgroup slot, each through the workgroup bitmap over its request's rows.
-template <bool NUM, typename V>
-__global__ __launch_bounds__(BATCH_WG_THREADS) void k_batch_wg(BatchArgs b, KArgs a) {
+template <int THREADS, bool NUM, typename V>
+__global__ __launch_bounds__(THREADS) void k_batch_wg(BatchArgs b, KArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ long long red[BATCH_WG_THREADS / 64 + 1];
+  __shared__ long long red[THREADS / 64 + 1];
   __shared__ int info;
   const int count = b.slotoff[BSLOTS + 1 + BSLOT_WG];
   const int off = b.slotoff[BSLOT_WG];
@@ -85,17 +85,24 @@ __global__ __launch_bounds__(BATCH_WG_THREADS) void k_batch_wg(BatchArgs b, KArg
     ta.colptr_c = q.colptr_c;
     ta.out_r = q.out_r;
     ta.out_v = q.out_v;
-    bitmap_wg_unit<BATCH_WG_THREADS, BATCH_WG_U / BATCH_WG_THREADS, NUM, false, V>(ta, smem, red, &info, 0,
-                                                                                 g - q.col_base, 0, 0, q.m);
+    bitmap_wg_unit<THREADS, BATCH_WG_U / THREADS, NUM, false, V>(ta, smem, red, &info, 0, g - q.col_base, 0, 0,
+                                                                q.m);
     __syncthreads();  // the next column rewrites the LDS this one may still read
   }
 }
 
-void launch_batch_wg(bool numeric, bool f64, const BatchArgs& b, const KArgs& a, unsigned blocks, hipStream_t s) {
+template <int THREADS>
+static void launch_wg_t(bool numeric, bool f64, const BatchArgs& b, const KArgs& a, unsigned blocks, hipStream_t s) {
   const size_t lds = (size_t)a.slice_bytes;
-  if (!numeric) k_batch_wg<false, float><<<blocks, BATCH_WG_THREADS, lds, s>>>(b, a);
-  else if (f64) k_batch_wg<true, double><<<blocks, BATCH_WG_THREADS, lds, s>>>(b, a);
-  else k_batch_wg<true, float><<<blocks, BATCH_WG_THREADS, lds, s>>>(b, a);
+  if (!numeric) k_batch_wg<THREADS, false, float><<<blocks, THREADS, lds, s>>>(b, a);
+  else if (f64) k_batch_wg<THREADS, true, double><<<blocks, THREADS, lds, s>>>(b, a);
+  else k_batch_wg<THREADS, true, float><<<blocks, THREADS, lds, s>>>(b, a);
+}
+
+void launch_batch_wg(bool numeric, bool f64, int threads, const BatchArgs& b, const KArgs& a, unsigned blocks,
+                     hipStream_t s) {
+  if (threads == 512) launch_wg_t<512>(numeric, f64, b, a, blocks, s);
+  else launch_wg_t<256>(numeric, f64, b, a, blocks, s);
 }
 
 int batch_fused_blocks_per_cu(bool numeric, bool f64, size_t lds) {

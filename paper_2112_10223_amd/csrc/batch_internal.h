@@ -30,14 +30,14 @@ struct BatchHdr {
 constexpr int BSLOT_EMPTY = 0;
 constexpr int BSLOT_LARGE = 1;
 constexpr int BSLOT_WAVE = 2;  // + 2 * (wave bin index) + (1 for the bitmap)
-// Workgroup-sized columns (1024 < u_j <= BATCH_WG_U) of requests with at most
-// BATCH_WG_SPAN rows: one workgroup bitmap each (larger columns are left to the
-// one-request path).
+// Workgroup-sized columns (wave_max < u_j <= wg_max <= BATCH_WG_U, by default 1024
+// and 4096) of requests with at most BATCH_WG_SPAN rows: one workgroup bitmap each
+// (larger columns are left to the one-request path).
 constexpr int BSLOT_WG = BSLOT_WAVE + 2 * NWAVE_BINS;
 constexpr int BSLOTS = BSLOT_WG + 1;
 constexpr int BATCH_WG_U = 4096;
 constexpr int BATCH_WG_SPAN = 1 << 17;
-constexpr int BATCH_WG_THREADS = 256;
+constexpr int BATCH_WG_THREADS = 256;  // default threads per workgroup of the workgroup slot (256 or 512)
 constexpr int BATCH_SCAN_THREADS = 1024;  // one workgroup per request scans its column counts
 constexpr int BATCH_MAX_BOUNDS_BLOCKS = 1024;
 constexpr int BATCH_CHUNK = 16;  // list entries per wavefront task
@@ -63,7 +63,8 @@ struct BatchArgs {
   int chunk;            // columns per bounds block (multiple of 256)
   int accum_mode;
   float bitmap_ratio;
-  int pad;
+  int wave_max;         // largest u_j of a wavefront slot
+  int wg_max;           // largest u_j of the workgroup slot (larger: the request is too large)
 };
 
 void launch_batch_plan(const BatchArgs& b, hipStream_t s);
@@ -76,7 +77,8 @@ void launch_batch_fused(bool numeric, bool f64, const BatchArgs& b, const KArgs&
                         hipStream_t s);
 // The workgroup-sized columns of one pass; `a` holds the common fields and the LDS
 // layout (lds_layout_bitmap_wg for BATCH_WG_SPAN rows, BATCH_WG_U entries, k = 64).
-void launch_batch_wg(bool numeric, bool f64, const BatchArgs& b, const KArgs& a, unsigned blocks, hipStream_t s);
+void launch_batch_wg(bool numeric, bool f64, int threads, const BatchArgs& b, const KArgs& a, unsigned blocks,
+                     hipStream_t s);
 // Blocks of the fused kernel resident per CU with `lds` bytes of LDS per block (0 if
 // the query fails).
 int batch_fused_blocks_per_cu(bool numeric, bool f64, size_t lds);

@@ -5,7 +5,7 @@
 //   k_batch_init    clears the per-request outcome and the counters (a kernel, so
 //                   the run can be captured in a graph)
 //   k_batch_bounds  u_j of every column (Section III-A) and its slot: empty, too
-//                   large for a wavefront (u_j > 1024), or (wave bin E, accumulator)
+//                   large for a wavefront (u_j > wave_max), or (wave bin E, accumulator)
 //   k_batch_slot_scan / k_batch_scatter  counting sort of the columns by slot;
 //                   inside a slot the columns keep their global order, so each
 //                   request's columns are contiguous
@@ -108,9 +108,9 @@ __global__ __launch_bounds__(256) void k_batch_bounds(BatchArgs b) {
       b.colcnt[g] = 0;
       if (u <= 0) {
         slot = BSLOT_EMPTY;
-      } else if (u > 1024 && u <= BATCH_WG_U && q.m <= BATCH_WG_SPAN) {
+      } else if (u > b.wave_max && u <= b.wg_max && q.m <= BATCH_WG_SPAN) {
         slot = BSLOT_WG;
-      } else if (u > 1024) {
+      } else if (u > b.wave_max) {
         slot = BSLOT_LARGE;
         atomicOr(&b.status[r], REQ_TOO_LARGE);
       } else {

@@ -80,3 +80,100 @@ def test_tune_errors():
     with pytest.raises(binding.SpkaddError) as e:
         _tune(b, base=bad, reps=1)
     assert e.value.status == binding.SPKADD_ERR_INVALID
+
+
+def _request_dicts(batches, values_dtype):
+    import torch
+    reqs = []
+    for b in batches:
+        cps, ris, vas = to_device(b)
+        cap = max(b.nnz_in, 1)
+        reqs.append(dict(m=b.m, colptrs=cps, rowidxs=ris, values=vas,
+                         colptr_c=torch.empty(b.n + 1, dtype=torch.int32, device="cuda:0"),
+                         rowidx_c=torch.empty(cap, dtype=torch.int32, device="cuda:0"),
+                         values_c=torch.empty(cap, dtype=values_dtype, device="cuda:0"), cap_c=cap))
+    return reqs
+
+
+def test_batch_tuner_matches_oracle():
+    """The batched-path tuner on a sample of the request distribution (k up to 64, with
+    requests too long for a batched run): every trial keeps each request's nnz(B), the
+    best setting is cached under the sample's key (kind 1), and batched runs with it
+    (the too-large requests through the one-request path) match the oracle."""
+    import torch
+    from paper_2112_10223_amd import binding
+    note("batch tuner")
+    batches = workloads.request_stream(36, seed=93, max_nnz=1 << 18, values="int32f")
+    batches += [workloads.er(3000, 40, 64, 10.0, seed=94, values="int32f"),     # k = 64
+                workloads.er(20000, 10, 40, 100.0, seed=95, values="int32f")]   # u ~ 4000: workgroup or too large
+    reqs = _request_dicts(batches, torch.float32)
+    best, rep, trials = binding.tune_batch(reqs, binding.SPKADD_F32, reps=1)
+    assert rep["trials"] == len(trials) >= 8 and rep["failed"] == 0, rep
+    assert all(t["status"] == 0 and t["same_nnz"] and t["ms"] > 0 for t in trials)
+    assert 0 < rep["best_ms"] <= rep["default_ms"]
+    assert {t["opts"]["batch_run_size"] for t in trials} >= {8, 16, 32}
+    assert {t["opts"]["batch_wave_max"] for t in trials} >= {512, 768}
+    key = binding.tune_key_batch(len(batches), sum(b.m for b in batches), sum(b.n for b in batches),
+                                 sum(b.k for b in batches), sum(b.nnz_in for b in batches))
+    assert key.kind == 1 and rep["key"]["kind"] == 1 and rep["key"]["u_log2"] == key.u_log2
+    cached = binding.tune_lookup(key)
+    assert cached is not None
+    for f in binding.BATCH_TUNED_FIELDS:
+        assert getattr(cached, f) == getattr(best, f)
+    # every request with the tuned setting, against the oracle
+    R = best.batch_run_size
+    bt = binding.Batch(binding.SPKADD_F32, R, sum(b.n for b in batches), sum(b.k for b in batches), cached)
+    for g in range(0, len(reqs), R):
+        grp = reqs[g:g + R]
+        for q in grp:
+            q["colptr_c"].fill_(-7)
+        bt.run(grp, use_graph=True)
+        nnz, st = bt.results()
+        for b, q, z, s in zip(batches[g:g + R], grp, nnz, st):
+            ref = oracle.spkadd(b)
+            if s == binding.SPKADD_REQ_TOO_LARGE:
+                cp, r, v = binding.spkadd(b.m, q["colptrs"], q["rowidxs"], q["values"], cached)
+                got = (cp.cpu().numpy().astype(np.int64), r.cpu().numpy(), v.cpu().numpy())
+            else:
+                assert s == binding.SPKADD_REQ_OK and z == ref.nnz
+                got = (q["colptr_c"].cpu().numpy().astype(np.int64), q["rowidx_c"][:z].cpu().numpy(),
+                       q["values_c"][:z].cpu().numpy())
+            assert_matches(b, got, ref, exact_values=True)
+    bt.close()
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("kw", [dict(batch_wave_max=512, batch_wg_max=2048, batch_wg_threads=512),
+                                dict(batch_wave_max=256, batch_wg_max=256), dict(batch_wg_threads=512)])
+def test_batch_cutoffs_and_workgroup_size(kw):
+    """Lower wavefront and workgroup cutoffs and 512-thread workgroups: columns move
+    between the slots (and to the one-request path), results stay exact."""
+    import torch
+    from paper_2112_10223_amd import binding
+    note(f"batch cutoffs {kw}")
+    batches = workloads.request_stream(20, seed=96, max_nnz=1 << 18, values="int32f")
+    batches.append(workloads.er(6000, 30, 8, 300.0, seed=97, values="int32f"))  # u ~ 2400
+    reqs = _request_dicts(batches, torch.float32)
+    opts = binding.make_opts(**kw)
+    bt = binding.Batch(binding.SPKADD_F32, len(reqs), sum(b.n for b in batches), sum(b.k for b in batches), opts)
+    bt.run(reqs, use_graph=True)
+    nnz, st = bt.results()
+    wg_max = kw.get("batch_wg_max", 4096)
+    for b, q, z, s in zip(batches, reqs, nnz, st):
+        u = sum(np.diff(b.colptr[i]).astype(np.int64) for i in range(b.k))
+        too_large = bool((u > wg_max).any() or (b.m > (1 << 17) and (u > kw.get("batch_wave_max", 1024)).any()))
+        assert (s == binding.SPKADD_REQ_TOO_LARGE) == too_large
+        if too_large:
+            continue
+        ref = oracle.spkadd(b)
+        got = (q["colptr_c"].cpu().numpy().astype(np.int64), q["rowidx_c"][:z].cpu().numpy(),
+               q["values_c"][:z].cpu().numpy())
+        assert_matches(b, got, ref, exact_values=True)
+    bt.close()
+    with pytest.raises(binding.SpkaddError):
+        binding.Batch(binding.SPKADD_F32, 4, 100, 16, binding.make_opts(batch_wave_max=2048))
+    with pytest.raises(binding.SpkaddError):
+        binding.Batch(binding.SPKADD_F32, 4, 100, 16, binding.make_opts(batch_wave_max=1024, batch_wg_max=512))
+    with pytest.raises(binding.SpkaddError):
+        binding.Batch(binding.SPKADD_F32, 4, 100, 16, binding.make_opts(batch_wg_threads=384))
+    torch.cuda.synchronize()
