@@ -122,25 +122,76 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 3) -> None:
 
 
 # one stream, one run in flight, at most 8 requests per run: measured best for
-# p50 and p99 on this workload against 16, 32, 64 requests and two streams
+# served latency (p50 and p99) on this workload against 16, 32, 64 and two streams
 SERVER_CONFIG = {"n_streams": 1, "depth": 1, "max_batch": 8}
+SERVE_BUDGET = 64 << 30  # bytes of output memory the admitted requests may hold
+BYTES_PER_INPUT_NNZ = 20  # algorithmic bytes of a batched request per input entry (fp32, cf ~ 1)
 
 
-def measure_served(reqs, plain_service_s: float, plain_one, load: float = 0.8, seed: int = 7,
-                   server_config: dict | None = None) -> dict:
-    """Poisson arrivals at `load` times the rate one-request plain launches can sustain
-    (1 / mean plain service time).  (a) plain: each request at its arrival time, in
-    order, one at a time through plan / symbolic / numeric; (a') the same on four
-    streams from four host threads; (b) served: a submitter
+class RequestPool:
+    """Requests of the served workload drawn on the device: the first `size` shapes of
+    the unfiltered request distribution (workloads.request_specs: k ~ U{2..64}, m, n
+    log-uniform in [256, 65536], density log-uniform in [1e-4, 1e-2] per matrix), their
+    inputs resident in HBM."""
+
+    def __init__(self, size: int, values: str = "f32", seed: int = workloads.SEED + 5):
+        import torch
+        from paper_2112_10223_amd import binding
+        self.specs = workloads.request_specs(size, seed=seed)
+        self.reqs = []
+        for sp in self.specs:
+            cps, ris, vas = workloads.device_request(sp, values)
+            fb = cps[0].data_ptr()
+            nnz = int(sum(int(r.shape[0]) for r in ris))
+            self.reqs.append(dict(m=sp.m, n=sp.n, k=sp.k, nnz_in=nnz, cap_c=max(nnz, 1),
+                                  colptrs=binding.PtrArray(cps, True, fb), rowidxs=binding.PtrArray(ris, True, fb),
+                                  values=binding.PtrArray(vas, True, fb)))
+        torch.cuda.synchronize()
+        self.nnz_in = sum(q["nnz_in"] for q in self.reqs)
+        self.max_cap = max(q["cap_c"] for q in self.reqs)
+        self.max_n = max(q["n"] for q in self.reqs)
+
+
+class PlainRunner:
+    """The one-request path (plan, symbolic, numeric) with outputs in one of `slots`
+    preallocated buffers (a buffer per concurrent stream)."""
+
+    def __init__(self, pool: RequestPool, slots: int = 4):
+        import torch
+        dev = "cuda:0"
+        self.out = [(torch.empty(pool.max_n + 1, dtype=torch.int32, device=dev),
+                     torch.empty(pool.max_cap, dtype=torch.int32, device=dev),
+                     torch.empty(pool.max_cap, dtype=torch.float32, device=dev)) for _ in range(slots)]
+
+    def run(self, q, stream, slot: int = 0, opts=None):
+        from paper_2112_10223_amd import binding
+        cp, r, v = self.out[slot]
+        p = binding.spkadd_plan(q["m"], q["n"], q["colptrs"], q["rowidxs"], binding.SPKADD_F32, opts, stream)
+        binding.spkadd_symbolic(p, cp[:q["n"] + 1], stream)
+        binding.spkadd_numeric(p, q["values"], r, v, stream)
+        p.free()
+
+
+def _pct(v, p):
+    return round(float(np.percentile(np.asarray(v) * 1e3, p)), 3)
+
+
+def measure_served(pool: RequestPool, plain: PlainRunner, picks, plain_service_s: float, load: float, seed: int,
+                   opts=None, server_config: dict | None = None) -> dict:
+    """Poisson arrivals at `load` times the rate one-request launches sustain on one
+    stream (1 / mean plain service time); arrival t brings pool request picks[t].
+    (a) plain: each request at its arrival time, in order, one at a time; (a') the
+    same from four host threads, each with its own stream; (b) served: a submitter
     thread hands each request to the serving loop at its arrival time.  Latency =
-    completion - arrival; p50 / p99 over all requests."""
+    completion - arrival; p50 / p99 over all arrivals."""
     import threading
     import torch
     from paper_2112_10223_amd import binding
     rng = np.random.default_rng(seed)
     rate = load / plain_service_s
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
-    nnz_in = sum(int(q["cap_c"]) for q in reqs)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(picks)))
+    reqs = [pool.reqs[i] for i in picks]
+    nnz_in = sum(q["nnz_in"] for q in reqs)
 
     def wait_until(t0, t):
         while True:
@@ -150,18 +201,18 @@ def measure_served(reqs, plain_service_s: float, plain_one, load: float = 0.8, s
             if left > 2e-4:
                 time.sleep(left - 1e-4)
 
+    stream = binding._stream_ptr(None)
     # (a) plain, first come first served on one stream
     lat_plain = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for q, a in zip(reqs, arrivals):
         wait_until(t0, a)
-        plain_one(q)
+        plain.run(q, stream, 0, opts)
         torch.cuda.synchronize()
         lat_plain.append(time.perf_counter() - t0 - a)
     span_plain = time.perf_counter() - t0
-    # (a') plain on 4 streams: 4 host threads, each with its own stream, take the
-    # requests in arrival order as they become free
+    # (a') plain on 4 streams: 4 host threads take the requests in arrival order
     lat_p4 = [0.0] * len(reqs)
     nxt = [0]
     lock = threading.Lock()
@@ -169,7 +220,7 @@ def measure_served(reqs, plain_service_s: float, plain_one, load: float = 0.8, s
     torch.cuda.synchronize()
     t0 = time.perf_counter()
 
-    def worker(st):
+    def worker(w, st):
         sp = binding._stream_ptr(st)
         while True:
             with lock:
@@ -178,34 +229,31 @@ def measure_served(reqs, plain_service_s: float, plain_one, load: float = 0.8, s
             if i >= len(reqs):
                 return
             wait_until(t0, arrivals[i])
-            plain_one(reqs[i], sp)
+            plain.run(reqs[i], sp, w, opts)
             st.synchronize()
             lat_p4[i] = time.perf_counter() - t0 - arrivals[i]
 
-    ths = [threading.Thread(target=worker, args=(st,)) for st in streams]
+    ths = [threading.Thread(target=worker, args=(w, st)) for w, st in enumerate(streams)]
     for th in ths:
         th.start()
     for th in ths:
         th.join()
     span_p4 = time.perf_counter() - t0
     # (b) the serving loop
-    cols = max(int(q["colptr_c"].shape[0]) for q in reqs)
     sc = dict(SERVER_CONFIG, **(server_config or {}))
     srv = binding.Server(binding.SPKADD_F32, n_streams=sc["n_streams"], max_batch=sc["max_batch"],
-                         max_columns=max(sc["max_batch"] * cols, 1 << 16), max_inputs=sc["max_batch"] * 64,
-                         hbm_budget=32 << 30, depth=sc["depth"])
+                         max_columns=max(sc["max_batch"] * pool.max_n, 1 << 17), max_inputs=sc["max_batch"] * 64,
+                         hbm_budget=SERVE_BUDGET, depth=sc["depth"], opts=opts)
     tickets = [None] * len(reqs)
-    sub_t = [0.0] * len(reqs)
 
     def submitter(t0s):
         for i, (q, a) in enumerate(zip(reqs, arrivals)):
             wait_until(t0s, a)
-            sub_t[i] = srv.now()
             tickets[i] = srv.submit(q["m"], q["colptrs"], q["rowidxs"], q["values"], q["cap_c"])
 
-    # warm-up: the whole sample once through the server, all at once (captures the
-    # launch shapes of full batches, which cover most of the smaller ones later)
-    warm = [srv.submit(q["m"], q["colptrs"], q["rowidxs"], q["values"], q["cap_c"]) for q in reqs]
+    # warm-up: the pool once through the server, all at once (captures the launch
+    # shapes of full runs, which cover most smaller ones later)
+    warm = [srv.submit(q["m"], q["colptrs"], q["rowidxs"], q["values"], q["cap_c"]) for q in pool.reqs]
     for tk in warm:
         srv.wait(tk)
         srv.release(tk)
@@ -229,115 +277,240 @@ def measure_served(reqs, plain_service_s: float, plain_one, load: float = 0.8, s
     srv.close()
     timed = {key: info[key] - info0[key] for key in ("runs", "batched", "large", "allocations", "graphs_captured",
                                                      "graph_reuses")}
-    pct = lambda v, p: round(float(np.percentile(np.asarray(v) * 1e3, p)), 3)
-    return {"arrival_rate_per_s": round(rate, 1), "load_vs_plain": load, "requests": len(reqs), "server": sc,
-            "plain": {"p50_ms": pct(lat_plain, 50), "p99_ms": pct(lat_plain, 99),
-                      "nnz_per_s": nnz_in / span_plain},
-            "plain_4_streams": {"p50_ms": pct(lat_p4, 50), "p99_ms": pct(lat_p4, 99), "nnz_per_s": nnz_in / span_p4},
-            "served": {"p50_ms": pct(lat_srv, 50), "p99_ms": pct(lat_srv, 99), "nnz_per_s": nnz_in / span_srv,
-                       "one_request_path": int(sum(paths)), "p50_admission_wait_ms": pct(qwait, 50),
-                       "p50_run_ms": pct(run, 50), "timed_region": timed},
-            "p99_speedup": round(pct(lat_plain, 99) / max(pct(lat_srv, 99), 1e-9), 3)}
+    lane = [x for x, p in zip(lat_srv, paths) if p == 1]
+    return {"arrival_rate_per_s": round(rate, 1), "load_vs_plain": load, "arrivals": len(reqs), "server": sc,
+            "plain": {"p50_ms": _pct(lat_plain, 50), "p99_ms": _pct(lat_plain, 99), "nnz_per_s": nnz_in / span_plain},
+            "plain_4_streams": {"p50_ms": _pct(lat_p4, 50), "p99_ms": _pct(lat_p4, 99),
+                                "nnz_per_s": nnz_in / span_p4},
+            "served": {"p50_ms": _pct(lat_srv, 50), "p99_ms": _pct(lat_srv, 99), "nnz_per_s": nnz_in / span_srv,
+                       "one_request_lane": {"share": round(len(lane) / len(reqs), 4),
+                                            "p50_ms": _pct(lane, 50) if lane else None,
+                                            "p99_ms": _pct(lane, 99) if lane else None},
+                       "p50_admission_wait_ms": _pct(qwait, 50), "p50_run_ms": _pct(run, 50), "timed_region": timed},
+            "p99_speedup_vs_plain": round(_pct(lat_plain, 99) / max(_pct(lat_srv, 99), 1e-9), 3),
+            "p99_speedup_vs_plain_4_streams": round(_pct(lat_p4, 99) / max(_pct(lat_srv, 99), 1e-9), 3)}
 
 
-def measure_batched(count: int = 120, batch_size: int = 40, max_nnz: int = 1 << 20, reps: int = 3,
-                    serve: bool = True):
-    """Small requests of the batched / served workload (a bounded sample: requests
-    whose expected input nnz exceeds max_nnz are redrawn), run (a) one request at a
-    time through plan / symbolic / numeric, (b) batch_size requests per batched run
-    through the captured graph, two batch objects alternating so the host prepares
-    one run while the other executes; requests a batch reports as too large for a
-    wavefront go through the one-request path.  Both timed over the whole sample."""
+def batched_throughput(pool: RequestPool, plain: PlainRunner, opts, run_size: int, reps: int = 3) -> dict:
+    """Every pool request through batched runs of run_size requests (two batch objects
+    alternate, each with an output arena of its largest group; graphs captured in a
+    warm-up pass); the requests a run reports too large go through the one-request
+    path.  Best of reps; also the device time of one run against its host call."""
     import torch
     from paper_2112_10223_amd import binding
-    reqs_h = workloads.request_stream(count, max_nnz=max_nnz)
-    dev = torch.device("cuda:0")
-    nnz_in = sum(r.nnz_in for r in reqs_h)
-    reqs = []
-    for r in reqs_h:
-        cps = [torch.from_numpy(np.ascontiguousarray(r.colptr[i])).to(dev) for i in range(r.k)]
-        ris = [torch.from_numpy(x).to(dev) for x in r.rowidx]
-        vas = [torch.from_numpy(x).to(dev) for x in r.vals]
-        cap = max(r.nnz_in, 1)
-        reqs.append(dict(m=r.m, colptrs=binding.PtrArray(cps, True), rowidxs=binding.PtrArray(ris, True),
-                         values=binding.PtrArray(vas, True), colptr_c=torch.empty(r.n + 1, dtype=torch.int32, device=dev),
-                         rowidx_c=torch.empty(cap, dtype=torch.int32, device=dev),
-                         values_c=torch.empty(cap, dtype=torch.float32, device=dev), cap_c=cap, keep=(cps, ris, vas)))
     stream = binding._stream_ptr(None)
-
-    def plain_one(q, s=None):
-        s = stream if s is None else s
-        p = binding.spkadd_plan(q["m"], q["colptr_c"].shape[0] - 1, q["colptrs"], q["rowidxs"], binding.SPKADD_F32,
-                                None, s)
-        binding.spkadd_symbolic(p, q["colptr_c"], s)
-        binding.spkadd_numeric(p, q["values"], q["rowidx_c"], q["values_c"], s)
-        p.free()
-
-    def plain_all():
-        for q in reqs:
-            plain_one(q)
-
-    groups = [reqs[i:i + batch_size] for i in range(0, len(reqs), batch_size)]
-    total_cols = max(sum(q["colptr_c"].shape[0] - 1 for q in g) for g in groups)
-    total_inputs = max(sum(len(q["colptrs"]) for q in g) for g in groups)
-    bts = [binding.Batch(binding.SPKADD_F32, batch_size, total_cols, total_inputs) for _ in range(2)]
+    groups = [pool.reqs[i:i + run_size] for i in range(0, len(pool.reqs), run_size)]
+    cols = max(sum(q["n"] for q in g) for g in groups)
+    inputs = max(sum(q["k"] for q in g) for g in groups)
+    arena_entries = max(sum(q["cap_c"] for q in g) for g in groups)
+    arena_cols = max(sum(q["n"] + 1 for q in g) for g in groups)
+    bts = [binding.Batch(binding.SPKADD_F32, run_size, cols, inputs, opts) for _ in range(2)]
+    arenas = [(torch.empty(arena_cols, dtype=torch.int32, device="cuda:0"),
+               torch.empty(arena_entries, dtype=torch.int32, device="cuda:0"),
+               torch.empty(arena_entries, dtype=torch.float32, device="cuda:0")) for _ in range(2)]
+    runs = []
+    for gi, g in enumerate(groups):
+        cp, r, v = arenas[gi & 1]
+        oc = oe = 0
+        rq = []
+        for q in g:
+            rq.append(dict(m=q["m"], colptrs=q["colptrs"], rowidxs=q["rowidxs"], values=q["values"],
+                           colptr_c=cp[oc:oc + q["n"] + 1], rowidx_c=r[oe:oe + q["cap_c"]],
+                           values_c=v[oe:oe + q["cap_c"]], cap_c=q["cap_c"], src=q))
+            oc += q["n"] + 1
+            oe += q["cap_c"]
+        runs.append(rq)
     large = []
 
-    def batched_all():
+    def one_pass():
         large.clear()
         pending = [None, None]
-        for gi, g in enumerate(groups):
+        for gi, rq in enumerate(runs):
             bt = bts[gi & 1]
             if pending[gi & 1] is not None:
                 _, st = bt.results()
-                large.extend(q for q, s in zip(pending[gi & 1], st) if s == binding.SPKADD_REQ_TOO_LARGE)
-            bt.run(g, use_graph=True, stream=stream)
-            pending[gi & 1] = g
+                large.extend(x["src"] for x, s in zip(pending[gi & 1], st) if s == binding.SPKADD_REQ_TOO_LARGE)
+            bt.run(rq, use_graph=True, stream=stream)
+            pending[gi & 1] = rq
         for slot in (0, 1):
             if pending[slot] is not None:
                 _, st = bts[slot].results()
-                large.extend(q for q, s in zip(pending[slot], st) if s == binding.SPKADD_REQ_TOO_LARGE)
+                large.extend(x["src"] for x, s in zip(pending[slot], st) if s == binding.SPKADD_REQ_TOO_LARGE)
         for q in large:
-            plain_one(q)
+            plain.run(q, stream, 0, opts)
 
-    times = {}
-    for name, fn in (("plain", plain_all), ("batched", batched_all)):
-        fn()  # warm-up (captures the graphs)
+    one_pass()  # warm-up (captures the graphs)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        one_pass()
         torch.cuda.synchronize()
-        best = None
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            best = dt if best is None else min(best, dt)
-        times[name] = best
-    # the two paths agree on every request's nnz(B)
-    nnz_b = []
-    for g in groups:
-        bts[0].run(g, use_graph=True, stream=stream)
-        nnz_b += bts[0].results()[0]
-    agree = 0
-    for q, z in zip(reqs, nnz_b):
-        if z >= 0:
-            plain_one(q)
-            torch.cuda.synchronize()
-            agree += int(int(q["colptr_c"][-1].item()) == z)
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    # one run of the largest group by device time (events on the stream) against its
+    # host call: the gap is host preparation and launch
+    gi = max(range(len(runs)), key=lambda x: sum(q["cap_c"] for q in runs[x]))
+    torch.cuda.synchronize()
+    ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ea.record()
+    bts[0].run(runs[gi], use_graph=True, stream=stream)
+    eb.record()
+    t_host = time.perf_counter() - t0
+    eb.synchronize()
+    t_wall = time.perf_counter() - t0
     info = bts[0].info()
     for bt in bts:
         bt.close()
-    # served: each entry a server configuration and an offered load (times what
-    # one-request launches sustain)
-    cases = serve if isinstance(serve, list) else [{"load": 0.5}, {"load": 0.8}, {"load": 1.5}] if serve else []
-    served = [measure_served(reqs, times["plain"] / len(reqs), plain_one, load=c.get("load", 0.8),
-                             server_config={k: v for k, v in c.items() if k != "load"}) for c in cases]
-    return served, {"requests": len(reqs), "batch_size": batch_size, "input_nnz": int(nnz_in),
-            "sample": f"{count} requests of the batched workload (k ~ U{{2..64}}, m, n log-U[256, 65536], "
-                      f"density log-U[1e-4, 1e-2] per matrix) with expected input nnz <= {max_nnz}",
-            "plain_ms": round(times["plain"] * 1e3, 3), "batched_ms": round(times["batched"] * 1e3, 3),
-            "plain_nnz_per_s": nnz_in / times["plain"], "batched_nnz_per_s": nnz_in / times["batched"],
-            "speedup": round(times["plain"] / times["batched"], 3), "too_large_routed_plain": len(large),
-            "kernels_per_batched_run": info["kernels_per_run"], "nnz_agree": f"{agree}/{sum(z >= 0 for z in nnz_b)}"}
+    nnz_batched = pool.nnz_in - sum(q["nnz_in"] for q in large)
+    return {"run_size": run_size, "ms": round(best * 1e3, 3), "nnz_per_s": pool.nnz_in / best,
+            "gbps_alg": round(BYTES_PER_INPUT_NNZ * pool.nnz_in / best / 1e9, 1),
+            "hbm_frac_alg": round(BYTES_PER_INPUT_NNZ * pool.nnz_in / best / 1e9 / HBM_PEAK_GBPS, 4),
+            "too_large_routed_plain": len(large), "input_nnz_in_batched_runs": int(nnz_batched),
+            "kernels_per_run": info["kernels_per_run"],
+            "one_run": {"requests": len(runs[gi]), "input_nnz": int(sum(q["src"]["nnz_in"] for q in runs[gi])),
+                        "device_ms": round(ea.elapsed_time(eb), 4), "host_call_ms": round(t_host * 1e3, 4),
+                        "wall_ms": round(t_wall * 1e3, 4)}}
+
+
+def alone_vs_mix(pool_size: int, picks, rate: float, seed: int, opts=None) -> dict:
+    """The bit-exact check of the served results on the integer-valued twin of the pool
+    (same patterns, values in {-3..3}): every pool request served alone, then every
+    arrival served in the mix at the given rate; each result's digest (colptr, rows and
+    values weighted by position, exact in int64 / fp64) must equal its alone digest."""
+    import threading
+    import torch
+    from paper_2112_10223_amd import binding
+    pool = RequestPool(pool_size, values="int32f")
+    sc = SERVER_CONFIG
+    srv = binding.Server(binding.SPKADD_F32, n_streams=sc["n_streams"], max_batch=sc["max_batch"],
+                         max_columns=max(sc["max_batch"] * pool.max_n, 1 << 17), max_inputs=sc["max_batch"] * 64,
+                         hbm_budget=SERVE_BUDGET, depth=sc["depth"], opts=opts)
+
+    def digest(res):
+        cp, r, v = srv.outputs(res)
+        w = torch.arange(r.numel(), device=r.device, dtype=torch.int64) % 1021 + 1
+        wc = torch.arange(cp.numel(), device=cp.device, dtype=torch.int64) % 1019 + 1
+        return (int(res["nnz"]), int((cp.to(torch.int64) * wc).sum()), int((r.to(torch.int64) * w).sum()),
+                float((v.to(torch.float64) * w.to(torch.float64)).sum()))
+
+    alone = []
+    for q in pool.reqs:
+        tk = srv.submit(q["m"], q["colptrs"], q["rowidxs"], q["values"], q["cap_c"])
+        res = srv.wait(tk)
+        alone.append(digest(res))
+        srv.release(tk)
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(picks)))
+    tickets = [None] * len(picks)
+
+    def submitter(t0):
+        for t, (i, a) in enumerate(zip(picks, arrivals)):
+            while time.perf_counter() - t0 < a:
+                time.sleep(0)
+            q = pool.reqs[i]
+            tickets[t] = srv.submit(q["m"], q["colptrs"], q["rowidxs"], q["values"], q["cap_c"])
+
+    th = threading.Thread(target=submitter, args=(time.perf_counter(),))
+    th.start()
+    same = lanes = 0
+    for t, i in enumerate(picks):
+        while tickets[t] is None:
+            time.sleep(0)
+        res = srv.wait(tickets[t])
+        lanes += res["path"]
+        same += int(digest(res) == alone[i])
+        srv.release(tickets[t])
+    th.join()
+    srv.close()
+    del pool
+    torch.cuda.empty_cache()
+    return {"values": "integer-valued twin of the pool (exact in any summation order)", "arrivals": len(picks),
+            "identical_to_alone": same, "differing": len(picks) - same, "one_request_lane": lanes}
+
+
+def measure_config5(pool_size: int = 1000, arrivals: int = 10000, side_arrivals: int = 2000,
+                    tune_sample: int = 250) -> dict:
+    """The batched / served workload at its stated size: a pool of pool_size requests of
+    the unfiltered request distribution (inputs drawn on the device), Poisson arrival
+    streams of `arrivals` requests drawn from the pool at load 0.8 (and side_arrivals at
+    loads 0.5 and 1.5) with a 64 GB output budget; batched throughput with the default
+    and the tuned batch setting (spkadd_tune_batch on a sample of the pool) against one
+    plain launch sequence per request; and the bit-exact alone-vs-mix check of every
+    arrival at load 0.8 on the pool's integer-valued twin."""
+    import torch
+    from paper_2112_10223_amd import binding
+    t_gen = time.perf_counter()
+    pool = RequestPool(pool_size)
+    t_gen = time.perf_counter() - t_gen
+    plain = PlainRunner(pool)
+    stream = binding._stream_ptr(None)
+    # one-request service time of every pool request (after one warm pass)
+    for q in pool.reqs:
+        plain.run(q, stream)
+    torch.cuda.synchronize()
+    svc = []
+    t_all = time.perf_counter()
+    for q in pool.reqs:
+        t0 = time.perf_counter()
+        plain.run(q, stream)
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t0)
+    t_all = time.perf_counter() - t_all
+    mean_svc = float(np.mean(svc))
+    big = [q["nnz_in"] > (1 << 24) for q in pool.reqs]
+    out = {"pool": {"requests": pool_size, "input_nnz": int(pool.nnz_in), "requests_over_2^24": int(sum(big)),
+                    "largest_input_nnz": int(max(q["nnz_in"] for q in pool.reqs)),
+                    "generation_s": round(t_gen, 2),
+                    "sample": f"the first {pool_size} requests of the unfiltered distribution (k ~ U{{2..64}}, "
+                              "m, n log-U[256, 65536], density log-U[1e-4, 1e-2] per matrix, fp32 U(-1,1)), "
+                              "drawn on the device; arrivals pick pool requests uniformly"},
+           "budget_bytes": SERVE_BUDGET,
+           "plain": {"mean_service_ms": round(mean_svc * 1e3, 4), "p99_service_ms": _pct(svc, 99),
+                     "nnz_per_s": pool.nnz_in / t_all,
+                     "gbps_alg": round(BYTES_PER_INPUT_NNZ * pool.nnz_in / t_all / 1e9, 1)}}
+    # batched throughput: default vs tuned
+    default = binding.make_opts()
+    out["batched_default"] = batched_throughput(pool, plain, default, 40)
+    rng = np.random.default_rng(11)
+    sample_idx = sorted(rng.choice(pool_size, size=min(tune_sample, pool_size), replace=False).tolist())
+    # the tuner's sample, each request with its own outputs (carved from one arena)
+    tot = sum(pool.reqs[i]["cap_c"] for i in sample_idx)
+    tc = sum(pool.reqs[i]["n"] + 1 for i in sample_idx)
+    a_cp = torch.empty(tc, dtype=torch.int32, device="cuda:0")
+    a_r = torch.empty(tot, dtype=torch.int32, device="cuda:0")
+    a_v = torch.empty(tot, dtype=torch.float32, device="cuda:0")
+    sample = []
+    oc = oe = 0
+    for i in sample_idx:
+        q = pool.reqs[i]
+        sample.append(dict(m=q["m"], colptrs=q["colptrs"], rowidxs=q["rowidxs"], values=q["values"],
+                           colptr_c=a_cp[oc:oc + q["n"] + 1], rowidx_c=a_r[oe:oe + q["cap_c"]],
+                           values_c=a_v[oe:oe + q["cap_c"]], cap_c=q["cap_c"]))
+        oc += q["n"] + 1
+        oe += q["cap_c"]
+    best, rep, trials = binding.tune_batch(sample, binding.SPKADD_F32, reps=2)
+    del sample, a_cp, a_r, a_v
+    torch.cuda.empty_cache()
+    out["batch_tuner"] = {"sample_requests": len(sample_idx), "trials": rep["trials"], "failed": rep["failed"],
+                          "default_ms": round(rep["default_ms"], 3), "best_ms": round(rep["best_ms"], 3),
+                          "best": {f: getattr(best, f) for f in binding.BATCH_TUNED_FIELDS}}
+    out["batched_tuned"] = batched_throughput(pool, plain, best, best.batch_run_size)
+    out["batched_speedup_tuned_vs_plain"] = round(out["batched_tuned"]["nnz_per_s"] / out["plain"]["nnz_per_s"], 3)
+    out["batched_speedup_tuned_vs_default"] = round(out["batched_tuned"]["nnz_per_s"] /
+                                                    out["batched_default"]["nnz_per_s"], 3)
+    # served
+    served = []
+    for load, count, seed in ((0.8, arrivals, 7), (0.5, side_arrivals, 8), (1.5, side_arrivals, 9)):
+        picks = np.random.default_rng(100 + seed).integers(0, pool_size, size=count).tolist()
+        served.append(measure_served(pool, plain, picks, mean_svc, load, seed, opts=best))
+    out["served"] = served
+    del plain, pool
+    torch.cuda.empty_cache()
+    picks = np.random.default_rng(107).integers(0, pool_size, size=arrivals).tolist()
+    out["alone_vs_mix"] = alone_vs_mix(pool_size, picks, 0.8 / mean_svc, 7, opts=best)
+    return out
 
 
 def cpu_baseline(batch, max_cols: int | None = None):
@@ -635,8 +808,10 @@ def main() -> int:
     ap.add_argument("--ordered", action="store_true", help="values summed in input order (SPKADD_FLAG_ORDERED)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison with the heap-merge and 2-way-tree baselines")
-    ap.add_argument("--batched", type=int, default=400,
-                    help="requests of the batched-vs-plain measurement (0 = skip)")
+    ap.add_argument("--served", type=int, default=10000,
+                    help="arrivals of the served stream at load 0.8 (0 = skip the batched / served workload)")
+    ap.add_argument("--served-pool", type=int, default=1000,
+                    help="distinct requests of the served workload (drawn on the device)")
     ap.add_argument("--no-sub", action="store_true",
                     help="time only --workload (not also the fp64, tall-skinny and R-MAT workloads)")
     args = ap.parse_args()
@@ -700,8 +875,8 @@ def main() -> int:
         out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(batch)
     del cps, ris, vas, batch
     torch.cuda.empty_cache()
-    if args.batched > 0:
-        out["served"], out["batched"] = measure_batched(args.batched)
+    if args.served > 0:
+        out["config5"] = measure_config5(pool_size=args.served_pool, arrivals=args.served)
         torch.cuda.empty_cache()
     if not args.no_sub and not (args.unsorted_in or args.unsorted_out or args.ordered or args.tune):
         subs = {}

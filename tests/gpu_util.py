@@ -82,10 +82,30 @@ def assert_matches(batch, got, ref, cols=None, exact_values=False):
     if exact_values:
         assert np.array_equal(gv.astype(np.float64), ref.val.astype(np.float64)), "values differ"
     else:
-        diff = np.abs(gv.astype(np.longdouble) - ref.val)
-        bound = value_bound(batch, ref)
+        idx = None
+        if batch.vals[0].dtype == np.float32:
+            # fast pass in float64: the margins (2^-40 of the bound, 2^-50 * sum|a|) exceed
+            # every rounding of these float64 steps, so an entry passing here is within
+            # the bound; the others are checked exactly below
+            s64 = ref.abs.astype(np.float64)
+            bound64 = np.maximum(np.float64(batch.k), ref.mult.astype(np.float64)) * F32_UNIT * s64
+            diff64 = np.abs(gv.astype(np.float64) - ref.val.astype(np.float64))
+            idx = np.nonzero(~(diff64 <= bound64 * (1.0 - 2.0 ** -40) - 2.0 ** -50 * s64))[0]
+            if idx.shape[0] == 0:
+                return
+        sub = ref if idx is None else _Sub(ref, idx)
+        sv = gv if idx is None else gv[idx]
+        diff = np.abs(sv.astype(np.longdouble) - sub.val)
+        bound = value_bound(batch, sub)
         bad = diff > bound
         assert not bad.any(), f"{int(bad.sum())} values outside k*u*sum|a| (max excess {float((diff - bound).max())})"
+
+
+class _Sub:
+    """The entries idx of an oracle result (val, abs, mult)."""
+
+    def __init__(self, ref, idx):
+        self.val, self.abs, self.mult = ref.val[idx], ref.abs[idx], ref.mult[idx]
 
 
 def check_properties(batch, colptr, rowidx):

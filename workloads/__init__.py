@@ -118,17 +118,19 @@ def _ptrs(arrays):
 
 
 def er(m: int, n: int, k: int, d: float, *, seed: int = SEED, fixed: bool = False, window: int = 0,
-       values: str = "f32") -> CSCBatch:
+       values: str = "f32", portable: bool = False) -> CSCBatch:
     """k ER matrices m x n; each column holds c distinct uniform rows.
 
     c ~ Poisson(d), or c = round(d) when ``fixed``.  A positive ``window`` draws
     each column's rows from `window` consecutive rows at a seeded per-column
-    offset (the same offset in all k inputs)."""
+    offset (the same offset in all k inputs).  ``portable`` draws the Poisson counts
+    with the sampler the device generator (gen_device.hip) shares, so the device can
+    produce the same matrices (d <= 700, no window)."""
     lib = _load()
     colptr = np.zeros((k, n + 1), dtype=np.int32)
     nnz = np.zeros(k, dtype=np.int64)
-    rc = lib.gen_er_counts(seed, m, n, k, 1 if fixed else 0, float(d), window, colptr.ctypes.data,
-                           nnz.ctypes.data)
+    mode = 1 if fixed else 2 if portable else 0
+    rc = lib.gen_er_counts(seed, m, n, k, mode, float(d), window, colptr.ctypes.data, nnz.ctypes.data)
     if rc != 0:
         raise ValueError("ER input too large for int32 column pointers")
     kind = VALUE_KINDS[values]
@@ -219,12 +221,31 @@ def stack(batches) -> CSCBatch:
     return CSCBatch(m, n, colptr, [r for b in batches for r in b.rowidx], [v for b in batches for v in b.vals])
 
 
-def request_stream(count: int, *, seed: int = SEED + 5, max_nnz: int | None = None, values: str = "f32"):
-    """Requests of the batched / served workload: k ~ U{2..64}; m and n independent
+@dataclass
+class RequestSpec:
+    """The shape of one request of the batched / served workload (draw number t of the
+    stream): k matrices m x n, matrix i with density dens[i] and seed matrix_seed(i)."""
+
+    t: int
+    k: int
+    m: int
+    n: int
+    dens: np.ndarray
+    seed: int
+
+    def matrix_seed(self, i: int) -> int:
+        return self.seed * 7919 + self.t * 131 + i
+
+    @property
+    def expected_nnz(self) -> float:
+        return float(self.dens.sum()) * self.m * self.n
+
+
+def request_specs(count: int, *, seed: int = SEED + 5, max_nnz: int | None = None):
+    """Shapes of the batched / served workload: k ~ U{2..64}; m and n independent
     log-uniform in [256, 65536]; each of the k matrices with its own density,
-    log-uniform in [1e-4, 1e-2], and Poisson(density * m) distinct uniform rows per
-    column.  With max_nnz, requests whose expected input nnz exceeds it are redrawn
-    (a bounded sample of the small-request part of the stream)."""
+    log-uniform in [1e-4, 1e-2].  With max_nnz, requests whose expected input nnz
+    exceeds it are redrawn (a bounded sample of the small-request part of the stream)."""
     rng = np.random.default_rng(seed)
     out = []
     t = 0
@@ -236,6 +257,82 @@ def request_stream(count: int, *, seed: int = SEED + 5, max_nnz: int | None = No
         dens = np.exp(rng.uniform(np.log(1e-4), np.log(1e-2), size=k))
         if max_nnz is not None and float(dens.sum()) * m * n > max_nnz:
             continue
-        mats = [er(m, n, 1, float(d * m), seed=seed * 7919 + t * 131 + i, values=values) for i, d in enumerate(dens)]
-        out.append(stack(mats))
+        out.append(RequestSpec(t, k, m, n, dens, seed))
     return out
+
+
+def request_from_spec(spec: RequestSpec, values: str = "f32") -> CSCBatch:
+    """The request's matrices on the host: matrix i holds Poisson(dens[i] * m) distinct
+    uniform rows per column (the portable sampler, so device_request draws the same)."""
+    return stack([er(spec.m, spec.n, 1, float(d * spec.m), seed=spec.matrix_seed(i), values=values, portable=True)
+                  for i, d in enumerate(spec.dens)])
+
+
+def request_stream(count: int, *, seed: int = SEED + 5, max_nnz: int | None = None, values: str = "f32"):
+    """Requests of the batched / served workload on the host (request_specs, then
+    request_from_spec)."""
+    return [request_from_spec(s, values) for s in request_specs(count, seed=seed, max_nnz=max_nnz)]
+
+
+# ---- the same ER matrices drawn on the device (gen_device.hip) ----
+_DEV_LIB_PATH = os.path.join(_HERE, "libgendev.so")
+_dev_lib = None
+
+
+def build_device_lib(force: bool = False) -> str:
+    """Compile gen_device.hip for gfx950 into libgendev.so next to it."""
+    if force or not os.path.exists(_DEV_LIB_PATH):
+        tmp = _DEV_LIB_PATH + ".tmp"
+        subprocess.check_call(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                               "-Wno-unused-command-line-argument", "-o", tmp,
+                               os.path.join(_HERE, "gen_device.hip")])
+        os.replace(tmp, _DEV_LIB_PATH)
+    return _DEV_LIB_PATH
+
+
+def _load_dev():
+    global _dev_lib
+    if _dev_lib is None:
+        if not os.path.exists(_DEV_LIB_PATH):
+            raise ImportError(f"{_DEV_LIB_PATH} is not built (workloads.build_device_lib())")
+        lib = ctypes.CDLL(_DEV_LIB_PATH)
+        P = ctypes.c_void_p
+        lib.gendev_er_counts.argtypes = [ctypes.c_int, ctypes.c_longlong, ctypes.c_longlong, P, P, P, P, P]
+        lib.gendev_er_counts.restype = ctypes.c_int
+        lib.gendev_er_fill.argtypes = [ctypes.c_int, ctypes.c_longlong, ctypes.c_longlong, P, P, P, P, ctypes.c_int, P]
+        lib.gendev_er_fill.restype = ctypes.c_int
+        _dev_lib = lib
+    return _dev_lib
+
+
+def device_request(spec: RequestSpec, values: str = "f32", device: str = "cuda:0", stream=None):
+    """The request's matrices drawn on the device: (colptrs, rowidxs, values), k torch
+    tensors each, equal to request_from_spec(spec, values) entry for entry."""
+    import torch
+    lib = _load_dev()
+    kind = VALUE_KINDS[values]
+    if kind == VALUE_KINDS["normal"]:
+        raise ValueError("normal values are drawn on the host only")
+    k, m, n = spec.k, spec.m, spec.n
+    s = torch.cuda.current_stream(device) if stream is None else stream
+    sp = ctypes.c_void_p(s.cuda_stream)
+    seeds = (ctypes.c_uint64 * k)(*[spec.matrix_seed(i) for i in range(k)])
+    means = (ctypes.c_double * k)(*[float(d * m) for d in spec.dens])
+    cp = torch.empty((k, n + 1), dtype=torch.int32, device=device)
+    cps = [cp[i] for i in range(k)]
+    cpp = (ctypes.c_void_p * k)(*[c.data_ptr() for c in cps])
+    nnz = torch.empty(k, dtype=torch.int64, device=device)
+    if lib.gendev_er_counts(k, m, n, seeds, means, cpp, ctypes.c_void_p(nnz.data_ptr()), sp) != 0:
+        raise RuntimeError("device generator: counts failed")
+    z = nnz.cpu().tolist()  # (waits for the counts)
+    if min(z) < 0:
+        raise ValueError("ER input too large for int32 column pointers")
+    dt = torch.float32 if VALUE_DTYPES[kind] == np.float32 else torch.float64
+    ris = [torch.empty(max(int(v), 1), dtype=torch.int32, device=device)[:int(v)] for v in z]
+    vas = [torch.empty(max(int(v), 1), dtype=dt, device=device)[:int(v)] for v in z]
+    rp = (ctypes.c_void_p * k)(*[r.data_ptr() for r in ris])
+    vp = (ctypes.c_void_p * k)(*[v.data_ptr() for v in vas])
+    if lib.gendev_er_fill(k, m, n, seeds, cpp, rp, vp, kind, sp) != 0:
+        raise RuntimeError("device generator: fill failed")
+    return cps, ris, vas

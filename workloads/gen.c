@@ -113,6 +113,41 @@ static int64_t poisson(double lambda, uint64_t key) {
   return x;
 }
 
+/* e^-lambda for 0 <= lambda <= 700 from basic arithmetic only: the alternating
+ * Taylor series of e^-(lambda/1024), then ten squarings.  Every step is one IEEE
+ * double operation in a fixed order, so a device copy of this routine (built without
+ * contraction into fused multiply-adds) returns the same bits. */
+static double exp_neg_series(double lambda) {
+  const double x = lambda / 1024.0;
+  double term = 1.0, sum = 1.0;
+  for (int t = 1; t <= 20; t++) {
+    term = term * x;
+    term = term / (double)t;
+    sum = (t & 1) ? sum - term : sum + term;
+  }
+  for (int s = 0; s < 10; s++) sum = sum * sum;
+  return sum;
+}
+
+/* Poisson(lambda) by inversion of the CDF from one uniform, with e^-lambda from
+ * exp_neg_series: the same count on the host and on the device (lambda <= 700;
+ * larger means fall back to poisson()). */
+static int64_t poisson_portable(double lambda, uint64_t key) {
+  if (lambda <= 0) return 0;
+  if (lambda > 700.0) return poisson(lambda, key);
+  const double u = u01_open(draw(key, 0));
+  double p = exp_neg_series(lambda), F = p;
+  int64_t x = 0;
+  const int64_t xmax = (int64_t)(20 * lambda + 100);
+  while (u > F && x < xmax) {
+    x++;
+    const double r = lambda / (double)x;
+    p = p * r;
+    F = F + p;
+  }
+  return x;
+}
+
 static int cmp_i32(const void* a, const void* b) {
   int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
   return (x > y) - (x < y);
@@ -163,7 +198,8 @@ static void distinct_rows(int32_t* out, int64_t c, int64_t lo, int64_t W, uint64
 }
 
 /*
- * ER / tall-skinny counts.  count_mode 0: c ~ Poisson(mean); 1: c = round(mean).
+ * ER / tall-skinny counts.  count_mode 0: c ~ Poisson(mean); 1: c = round(mean);
+ * 2: c ~ Poisson(mean) drawn by poisson_portable (the device generator's sampler).
  * Counts are clipped to the window width.  window > 0 draws each column's rows
  * from a window of `window` rows at a per-column seeded offset (same offset for
  * all k matrices); window <= 0 uses all m rows.
@@ -177,8 +213,9 @@ int gen_er_counts(uint64_t seed, int64_t m, int64_t n, int32_t k, int32_t count_
     cp[0] = 0;
     int64_t acc = 0;
     for (int64_t j = 0; j < n; j++) {
-      int64_t c = count_mode == 0 ? poisson(mean, stream_key(seed, TAG_COUNT, (uint64_t)i, (uint64_t)j))
-                                  : (int64_t)llround(mean);
+      const uint64_t ck = stream_key(seed, TAG_COUNT, (uint64_t)i, (uint64_t)j);
+      int64_t c = count_mode == 0 ? poisson(mean, ck) : count_mode == 2 ? poisson_portable(mean, ck)
+                                                                        : (int64_t)llround(mean);
       if (c > W) c = W;
       if (c < 0) c = 0;
       acc += c;
