@@ -53,6 +53,7 @@ struct PlanParams {
   float win_fill;   // target window input count = cap_in * win_fill
   int unsorted_in;  // input columns may be unsorted (validation checks only the row range)
   int win_min;      // fewest windows of a window column (each then at most the bitmap's rows)
+  int win_span;     // widest window left unsplit (the workgroup bitmap's rows; INT32_MAX without bitmaps)
 };
 
 // Summary written by the plan kernels; the host reads it from a pinned slot.
@@ -125,7 +126,10 @@ void launch_bin_scatter(const PlanParams& p, const unsigned char* d_bin, const i
                         int* d_list, hipStream_t s);
 void launch_win_scan(const PlanParams& p, const int* d_list, const int* d_binoff, const int* d_u, int* d_wfirst,
                      PlanSummary* d_sum, hipStream_t s);
-void launch_win_fill(const PlanParams& p, int n_wcols, const int* d_wfirst, int* d_win_c, int* d_brow, int* d_bcol,
+// First windows of the window columns: row quantiles of each column's longest input
+// (sorted inputs, columns of the binary-search kind), else equal row ranges.
+void launch_win_fill(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
+                     const int* d_u, int n_wcols, const int* d_wfirst, int* d_win_c, int* d_brow, int* d_bcol,
                      hipStream_t s);
 void launch_win_search(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
                        const int* d_wfirst, const int* d_u, int n_wcols, int n_bounds, const int* d_bcol,

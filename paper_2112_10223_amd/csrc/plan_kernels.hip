@@ -252,19 +252,113 @@ __global__ __launch_bounds__(1024) void k_win_scan(PlanParams p, const int* __re
   }
 }
 
-// Equal-row-range windows (the paper's split, Algorithms 7-8): window p of column c
-// covers rows [p*m/P, (p+1)*m/P).  Boundary b of column c has index wfirst[c] + c + p.
-__global__ __launch_bounds__(256) void k_win_fill(PlanParams p, int n_wcols, const int* __restrict__ wfirst,
-                                                  int* __restrict__ win_c, int* __restrict__ brow,
-                                                  int* __restrict__ bcol) {
+// Whether window column c's boundaries are found by one ordered pass over its rows
+// (k_win_search_lin) rather than a binary search per (boundary, input): when each
+// input holds 1024..8192 rows of the column on average (shorter: a wavefront mostly
+// waits on the loads that start each input; longer: a block's sequential pass over
+// its inputs outlasts the searches).
+__device__ __forceinline__ bool win_search_linear(long long u, int k) {
+  return u >= 1024LL * k && u <= 8192LL * k;
+}
+
+// First windows of each window column.  The paper splits a column's rows equally
+// (Algorithms 7-8: window q covers rows [q m / P, (q + 1) m / P)).  Here, where the
+// inputs are sorted and the column's boundaries are found by binary searches, the
+// boundaries are instead the row quantiles of the column's longest input (the row at
+// position floor(q len / P) of that input's column): for inputs of similar row
+// distributions -- independent R-MAT matrices, whose rows crowd the low indices --
+// every window then holds about u / P entries from the start, where equal row ranges
+// overfill the first windows and need several refinement rounds.  Any strictly
+// increasing boundaries from 0 to m give the same result; boundary q is forced to
+// q + max_{t <= q}(b_t - t) over the candidates b_t clamped to [t, m - P + t], which
+// is strictly increasing whatever the rows hold.  Boundary b of column c has index
+// wfirst[c] + c + q.
+__global__ __launch_bounds__(256) void k_win_fill(PlanParams p, const int* const* __restrict__ cp,
+                                                  const int* const* __restrict__ ri, const int* __restrict__ wcols,
+                                                  const int* __restrict__ u, int n_wcols,
+                                                  const int* __restrict__ wfirst, int* __restrict__ win_c,
+                                                  int* __restrict__ brow, int* __restrict__ bcol) {
+  __shared__ int wl[256 / 64], wi[256 / 64];
+  __shared__ int carry_s;
   const int c = blockIdx.x;
   if (c >= n_wcols) return;
   const int w0 = wfirst[c], P = wfirst[c + 1] - w0;
-  for (int q = threadIdx.x; q <= P; q += blockDim.x) {
-    const int b = w0 + c + q;
-    brow[b] = (int)(((long long)q * (long long)p.m) / P);
-    bcol[b] = c;
-    if (q < P) win_c[w0 + q] = c;
+  const int j = wcols[c];
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  // the longest input of the column (lowest index among equals)
+  int best_len = -1, best_i = 0;
+  const bool quant = P > 1 && !p.unsorted_in && !win_search_linear(u[j], p.k);
+  if (quant) {
+    for (int i = threadIdx.x; i < p.k; i += 256) {
+      const int* col = cp[i];
+      const int len = col[j + 1] - col[j];
+      if (len > best_len) {
+        best_len = len;
+        best_i = i;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const int ol = __shfl_xor(best_len, off, 64), oi = __shfl_xor(best_i, off, 64);
+      if (ol > best_len || (ol == best_len && oi < best_i)) {
+        best_len = ol;
+        best_i = oi;
+      }
+    }
+    if (lane == 0) {
+      wl[w] = best_len;
+      wi[w] = best_i;
+    }
+    __syncthreads();
+    best_len = wl[0];
+    best_i = wi[0];
+    for (int v = 1; v < 256 / 64; ++v)
+      if (wl[v] > best_len || (wl[v] == best_len && wi[v] < best_i)) {
+        best_len = wl[v];
+        best_i = wi[v];
+      }
+  }
+  const bool use_q = quant && best_len >= P;
+  const int* rows = use_q ? ri[best_i] + cp[best_i][j] : nullptr;
+  if (threadIdx.x == 0) carry_s = INT_MIN;
+  __syncthreads();
+  for (int base = 0; base <= P; base += 256) {
+    const int q = base + threadIdx.x;
+    int cand = INT_MIN;  // b_q - q
+    if (q <= P) {
+      long long b;
+      if (!use_q) {
+        b = ((long long)q * (long long)p.m) / P;
+      } else if (q == 0) {
+        b = 0;
+      } else if (q == P) {
+        b = p.m;
+      } else {
+        b = rows[(long long)q * best_len / P];
+        const long long lo = q, hi = (long long)p.m - P + q;
+        b = b < lo ? lo : b > hi ? hi : b;
+      }
+      cand = (int)(b - q);
+    }
+    // inclusive prefix max over the block, after the previous chunks' maximum
+    int pm = cand;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(pm, off, 64);
+      if (lane >= off) pm = max(pm, v);
+    }
+    __syncthreads();
+    if (lane == 63) wl[w] = pm;
+    __syncthreads();
+    for (int v = 0; v < w; ++v) pm = max(pm, wl[v]);
+    pm = max(pm, carry_s);
+    if (q <= P) {
+      const int b = w0 + c + q;
+      brow[b] = q + pm;
+      bcol[b] = c;
+      if (q < P) win_c[w0 + q] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 255) carry_s = pm;
+    __syncthreads();
   }
 }
 
@@ -279,14 +373,6 @@ __device__ __forceinline__ int lower_bound_rows(const int* __restrict__ r, int l
 
 // Position of every boundary row in every input column: bpos[b*k + i] = the first
 // entry of input i's column at or after boundary row b.
-// Whether window column c's boundaries are found by one ordered pass over its rows
-// (k_win_search_lin) rather than a binary search per (boundary, input): when each
-// input holds 1024..8192 rows of the column on average (shorter: a wavefront mostly
-// waits on the loads that start each input; longer: a block's sequential pass over
-// its inputs outlasts the searches).
-__device__ __forceinline__ bool win_search_linear(long long u, int k) {
-  return u >= 1024LL * k && u <= 8192LL * k;
-}
 
 // One binary search per (boundary, input), for the columns that do not take the
 // ordered pass.
@@ -389,10 +475,17 @@ __global__ __launch_bounds__(256) void k_win_count(PlanParams p, int n_windows, 
   const int width = brow[b + 1] - brow[b];
   atomicMax(&sum->max_span, width);
   int pieces = 1;
+  long long qq = 1;
   if (cnt > p.cap_in && width > p.cap_in) {
     const double target = (double)p.cap_in * (double)p.win_fill;
-    long long qq = (long long)ceil((double)cnt / (target > 1.0 ? target : 1.0));
+    qq = (long long)ceil((double)cnt / (target > 1.0 ? target : 1.0));
     if (qq < 2) qq = 2;
+  }
+  if (width > p.win_span) {  // wider than the workgroup bitmap: equal pieces that fit it
+    const long long qw = ((long long)width + p.win_span - 1) / p.win_span;
+    if (qw > qq) qq = qw;
+  }
+  if (qq > 1) {
     if (qq > width) qq = width;
     pieces = (int)qq;
     atomicAdd(&sum->pad, 1);  // number of windows still to refine
@@ -651,10 +744,11 @@ void launch_win_scan(const PlanParams& p, const int* d_list, const int* d_binoff
   k_win_scan<<<1, 1024, 0, s>>>(p, d_list, d_binoff, d_u, d_wfirst, d_sum);
 }
 
-void launch_win_fill(const PlanParams& p, int n_wcols, const int* d_wfirst, int* d_win_c, int* d_brow, int* d_bcol,
+void launch_win_fill(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
+                     const int* d_u, int n_wcols, const int* d_wfirst, int* d_win_c, int* d_brow, int* d_bcol,
                      hipStream_t s) {
   if (n_wcols == 0) return;
-  k_win_fill<<<n_wcols, 256, 0, s>>>(p, n_wcols, d_wfirst, d_win_c, d_brow, d_bcol);
+  k_win_fill<<<n_wcols, 256, 0, s>>>(p, d_cp, d_ri, d_wcols, d_u, n_wcols, d_wfirst, d_win_c, d_brow, d_bcol);
 }
 
 void launch_win_search(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,

@@ -515,7 +515,7 @@ spkadd_status build_windows(spkadd_plan_s* p, hipStream_t s) {
   const int* wcols = p->d_list + p->binoff[BIN_WIN];
   {
     TraceScope t(p, "win_fill", s);
-    launch_win_fill(p->pp, nwc, p->d_wfirst, p->d_win_c, p->d_brow, p->d_bcol, s);
+    launch_win_fill(p->pp, p->d_cp, p->d_ri, wcols, p->d_u, nwc, p->d_wfirst, p->d_win_c, p->d_brow, p->d_bcol, s);
   }
   {
     TraceScope t(p, "win_search", s);
@@ -622,7 +622,7 @@ spkadd_status build_windows_unsorted(spkadd_plan_s* p, hipStream_t s) {
   const int* wcols = p->d_list + p->binoff[BIN_WIN];
   {
     TraceScope t(p, "win_fill", s);
-    launch_win_fill(p->pp, nwc, p->d_wfirst, p->d_win_c, p->d_brow, p->d_bcol, s);
+    launch_win_fill(p->pp, p->d_cp, p->d_ri, wcols, p->d_u, nwc, p->d_wfirst, p->d_win_c, p->d_brow, p->d_bcol, s);
   }
   // work units of the passes over the columns' entries: chunks of each column
   int *d_nch = nullptr, *d_chfirst = nullptr, *d_chcol = nullptr;
@@ -906,8 +906,11 @@ spkadd_status plan_build(spkadd_plan_s* p, int32_t m, int32_t n, int32_t k, cons
   // windows no wider than the workgroup bitmap, so that none falls back to hash
   // tables (unless hash tables are asked for)
   p->pp.win_min = 1;
-  if (o.accum_mode != SPKADD_ACCUM_HASH && o.hash_mode == 0 && m > bitmap_wg_span_max())
+  p->pp.win_span = INT_MAX;
+  if (o.accum_mode != SPKADD_ACCUM_HASH && o.hash_mode == 0 && m > bitmap_wg_span_max()) {
     p->pp.win_min = (int)(((long long)m + bitmap_wg_span_max() - 1) / bitmap_wg_span_max());
+    p->pp.win_span = bitmap_wg_span_max();
+  }
   for (int b = BIN_W1; b <= BIN_W16; ++b) {
     p->ts_sym[b] = table_slots(64 * wave_bin_E(b), p->alpha_sym_q);
     p->ts_num[b] = table_slots(64 * wave_bin_E(b), p->alpha_num_q);
