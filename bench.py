@@ -122,8 +122,9 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 3) -> None:
 
 
 # one stream, one run in flight, at most 8 requests per run: measured best for
-# served latency (p50 and p99) on this workload against 16, 32, 64 and two streams
-SERVER_CONFIG = {"n_streams": 1, "depth": 1, "max_batch": 8}
+# served latency (p50 and p99) on this workload against 16, 32, 64 and two streams;
+# two one-request lanes for the requests too large for a batched run
+SERVER_CONFIG = {"n_streams": 1, "depth": 1, "max_batch": 8, "large_streams": 2}
 SERVE_BUDGET = 64 << 30  # bytes of output memory the admitted requests may hold
 BYTES_PER_INPUT_NNZ = 20  # algorithmic bytes of a batched request per input entry (fp32, cf ~ 1)
 
@@ -243,7 +244,7 @@ def measure_served(pool: RequestPool, plain: PlainRunner, picks, plain_service_s
     sc = dict(SERVER_CONFIG, **(server_config or {}))
     srv = binding.Server(binding.SPKADD_F32, n_streams=sc["n_streams"], max_batch=sc["max_batch"],
                          max_columns=max(sc["max_batch"] * pool.max_n, 1 << 17), max_inputs=sc["max_batch"] * 64,
-                         hbm_budget=SERVE_BUDGET, depth=sc["depth"], opts=opts)
+                         hbm_budget=SERVE_BUDGET, depth=sc["depth"], opts=opts, large_streams=sc["large_streams"])
     tickets = [None] * len(reqs)
 
     def submitter(t0s):
@@ -386,7 +387,7 @@ def alone_vs_mix(pool_size: int, picks, rate: float, seed: int, opts=None) -> di
     sc = SERVER_CONFIG
     srv = binding.Server(binding.SPKADD_F32, n_streams=sc["n_streams"], max_batch=sc["max_batch"],
                          max_columns=max(sc["max_batch"] * pool.max_n, 1 << 17), max_inputs=sc["max_batch"] * 64,
-                         hbm_budget=SERVE_BUDGET, depth=sc["depth"], opts=opts)
+                         hbm_budget=SERVE_BUDGET, depth=sc["depth"], opts=opts, large_streams=sc["large_streams"])
 
     def digest(res):
         cp, r, v = srv.outputs(res)

@@ -31,6 +31,9 @@
  *
  * Errors.  Every call returns a status and throws no exceptions.  spkadd_last_error()
  * gives a message for the calling thread.  On an error, outputs are unspecified.
+ * The plan, symbolic and numeric calls clear the HIP runtime's last-error state of
+ * the calling thread on entry (so that a stale status of the caller's own earlier
+ * HIP calls is not taken for a failure of theirs).
  * The plan stays usable unless the status is SPKADD_ERR_HIP, which marks it failed.
  * Argument checks run on the host before any device work.
  *

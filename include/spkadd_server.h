@@ -8,8 +8,8 @@
  * and completes the tickets.  A request that a batch reports as too large
  * (a column with more entries than opts.batch_wg_max, 4096 by default, or than
  * opts.batch_wave_max in a request of more than 2^17 rows) goes through the
- * one-request path (spkadd_plan / spkadd_symbolic / spkadd_numeric) on a stream of its
- * own.  Requests that arrive while others are on the device join the next run.
+ * one-request path (spkadd_plan / spkadd_symbolic / spkadd_numeric) on one of the
+ * one-request lanes (config large_streams), each with a stream of its own.  Requests that arrive while others are on the device join the next run.
  *
  * Outputs are allocated by the server (stream-ordered, or reused from released
  * tickets) with the capacity the request states in cap_c (sum_i nnz(A_i) always
@@ -41,7 +41,9 @@ typedef struct spkadd_server_config {
                               arrive while a stream's run executes wait and join its
                               next run (larger runs); with 2, the next run is enqueued
                               behind the running one */
-  int32_t reserved;
+  int32_t large_streams;   /* one-request lanes (0..8; 0 = 2): requests too large for a
+                              batched run are served on this many streams at once, each
+                              lane a host thread with its own stream */
   int64_t max_columns;     /* columns per batched run */
   int64_t max_inputs;      /* inputs (sum of k) per batched run */
   uint64_t hbm_budget;     /* bytes of output memory the admitted requests may hold */

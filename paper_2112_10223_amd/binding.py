@@ -369,7 +369,8 @@ SPKADD_REQ_ERROR = 3
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int), ("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("depth", ctypes.c_int32), ("reserved", ctypes.c_int32), ("max_columns", ctypes.c_int64), ("max_inputs", ctypes.c_int64), ("hbm_budget", ctypes.c_uint64),
+                ("depth", ctypes.c_int32), ("large_streams", ctypes.c_int32), ("max_columns", ctypes.c_int64),
+                ("max_inputs", ctypes.c_int64), ("hbm_budget", ctypes.c_uint64),
                 ("opts", ctypes.POINTER(Opts))]
 
 
@@ -428,10 +429,10 @@ class Server:
     """Owning handle of an spkadd_server_t (include/spkadd_server.h)."""
 
     def __init__(self, dtype=SPKADD_F32, n_streams=1, max_batch=8, max_columns=1 << 20, max_inputs=1 << 14,
-                 hbm_budget=64 << 30, opts: Opts | None = None, depth=1):
+                 hbm_budget=64 << 30, opts: Opts | None = None, depth=1, large_streams=0):
         L = _server_fns()
         self._opts = opts
-        cfg = ServerConfig(dtype, n_streams, max_batch, depth, 0, max_columns, max_inputs, hbm_budget,
+        cfg = ServerConfig(dtype, n_streams, max_batch, depth, large_streams, max_columns, max_inputs, hbm_budget,
                            ctypes.pointer(opts) if opts is not None else None)
         h = ctypes.c_void_p()
         _check(L.spkadd_server_create(ctypes.byref(h), ctypes.byref(cfg)))

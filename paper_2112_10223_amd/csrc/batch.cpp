@@ -332,6 +332,7 @@ spkadd_status spkadd_batch_create(spkadd_batch_t* out, spkadd_dtype dtype, int32
 
 spkadd_status spkadd_batch_run(spkadd_batch_t b, const spkadd_request* reqs, int32_t nreq, int32_t use_graph,
                                hipStream_t stream) {
+  (void)hipGetLastError();  // a stale status of the caller's earlier HIP calls
   if (!b) return fail(SPKADD_ERR_INVALID, "batch is NULL");
   if (nreq < 1 || nreq > b->max_reqs) return fail(SPKADD_ERR_INVALID, "nreq = %d (limit %d)", nreq, b->max_reqs);
   if (!reqs) return fail(SPKADD_ERR_INVALID, "reqs is NULL");

@@ -807,6 +807,9 @@ size_t scan_tmp_bytes(int64_t len) {
 
 void launch_scan(const int* d_in, int64_t len, int* d_out, long long* d_total, int* d_err, void* d_tmp,
                  hipStream_t s) {
+  // one workgroup for one tile; longer inputs in parallel tiles (measured: one
+  // workgroup walking the four tiles of 65536 counts takes 18 us, the two launches
+  // below 10 us)
   if (len <= SCAN_SMALL) {
     k_scan_small<<<1, SCAN_SMALL_THREADS, 0, s>>>(d_in, (int)len, d_total, d_out, d_err);
     return;

@@ -80,13 +80,15 @@ struct spkadd_server_s {
   uint64_t in_use = 0;
   bool stop = false;
   std::vector<Lane> lanes;
-  hipStream_t large_stream = nullptr, free_stream = nullptr;
+  std::vector<hipStream_t> large_streams;  // one per one-request lane
+  hipStream_t free_stream = nullptr;
   // released output blocks by size class (power of two, >= 64 KiB), reused by later
   // requests; held blocks and pooled ones together stay within the budget
   std::unordered_map<size_t, std::vector<char*>> pool;
   uint64_t pooled = 0;
   long long runs = 0, batched = 0, large_count = 0, allocations = 0;
-  std::thread loop, large_loop;
+  std::thread loop;
+  std::vector<std::thread> large_loops;
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -251,8 +253,10 @@ void server_loop(spkadd_server_s* s) {
   }
 }
 
-// Requests too large for a batch: plan / symbolic / numeric on a stream of their own.
-void large_loop(spkadd_server_s* s) {
+// Requests too large for a batch: plan / symbolic / numeric on a stream of their own
+// (one-request lane `lane`; the lanes take requests from one queue, in order).
+void large_loop(spkadd_server_s* s, int lane) {
+  hipStream_t stream = s->large_streams[(size_t)lane];
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
@@ -278,15 +282,15 @@ void large_loop(spkadd_server_s* s) {
     long long nnz = -1;
     int outcome = SPKADD_REQ_OK;
     spkadd_status st = spkadd_plan(&p, m, n, k, (const int32_t* const*)cp.data(), (const int32_t* const*)ri.data(),
-                                   s->cfg.dtype, &s->opts, s->large_stream);
+                                   s->cfg.dtype, &s->opts, stream);
     if (st == SPKADD_OK) {
       int64_t z = 0;
-      st = spkadd_symbolic(p, res.colptr_c, &z, s->large_stream);
+      st = spkadd_symbolic(p, res.colptr_c, &z, stream);
       nnz = z;
       if (st == SPKADD_OK && z > cap) outcome = SPKADD_REQ_CAPACITY;
       if (st == SPKADD_OK && outcome == SPKADD_REQ_OK)
-        st = spkadd_numeric(p, va.data(), res.rowidx_c, res.values_c, s->large_stream);
-      if (st == SPKADD_OK && hipStreamSynchronize(s->large_stream) != hipSuccess) {
+        st = spkadd_numeric(p, va.data(), res.rowidx_c, res.values_c, stream);
+      if (st == SPKADD_OK && hipStreamSynchronize(stream) != hipSuccess) {
         (void)hipGetLastError();
         st = SPKADD_ERR_HIP;
       }
@@ -312,6 +316,7 @@ spkadd_status spkadd_server_create(spkadd_server_t* out, const spkadd_server_con
   if (cfg->n_streams < 1 || cfg->n_streams > 8) return sfail(SPKADD_ERR_INVALID, "n_streams must be 1..8");
   if (cfg->max_batch < 0 || cfg->max_batch > 4096) return sfail(SPKADD_ERR_INVALID, "max_batch must be 0..4096");
   if (cfg->depth < 1 || cfg->depth > 2) return sfail(SPKADD_ERR_INVALID, "depth must be 1 or 2");
+  if (cfg->large_streams < 0 || cfg->large_streams > 8) return sfail(SPKADD_ERR_INVALID, "large_streams must be 0..8");
   if (cfg->max_columns < 1 || cfg->max_inputs < 1 || cfg->hbm_budget == 0)
     return sfail(SPKADD_ERR_INVALID, "max_columns, max_inputs and hbm_budget must be positive");
   auto* s = new (std::nothrow) spkadd_server_s();
@@ -320,6 +325,7 @@ spkadd_status spkadd_server_create(spkadd_server_t* out, const spkadd_server_con
   spkadd_opts_default(&s->opts);
   if (cfg->opts) s->opts = *cfg->opts;
   s->cfg.opts = nullptr;
+  if (s->cfg.large_streams == 0) s->cfg.large_streams = 2;
   if (s->cfg.max_batch == 0)  // the tuned run size, else 8
     s->cfg.max_batch = s->opts.batch_run_size > 0 && s->opts.batch_run_size <= 4096 ? s->opts.batch_run_size : 8;
   s->vbytes = cfg->dtype == SPKADD_F64 ? 8 : 4;
@@ -334,7 +340,8 @@ spkadd_status spkadd_server_create(spkadd_server_t* out, const spkadd_server_con
       for (auto& b : ln.batch) spkadd_batch_destroy(b);
       if (ln.stream) (void)hipStreamDestroy(ln.stream);
     }
-    if (s->large_stream) (void)hipStreamDestroy(s->large_stream);
+    for (hipStream_t ls : s->large_streams)
+      if (ls) (void)hipStreamDestroy(ls);
     if (s->free_stream) (void)hipStreamDestroy(s->free_stream);
     delete s;
     return sfail(st, "%s", what);
@@ -348,11 +355,13 @@ spkadd_status spkadd_server_create(spkadd_server_t* out, const spkadd_server_con
       if (st != SPKADD_OK) return cleanup(st, "batch creation failed");
     }
   }
-  if (hipStreamCreateWithFlags(&s->large_stream, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&s->free_stream, hipStreamNonBlocking) != hipSuccess)
+  s->large_streams.assign((size_t)s->cfg.large_streams, nullptr);
+  for (hipStream_t& ls : s->large_streams)
+    if (hipStreamCreateWithFlags(&ls, hipStreamNonBlocking) != hipSuccess) return cleanup(SPKADD_ERR_HIP, "stream");
+  if (hipStreamCreateWithFlags(&s->free_stream, hipStreamNonBlocking) != hipSuccess)
     return cleanup(SPKADD_ERR_HIP, "stream");
   s->loop = std::thread(server_loop, s);
-  s->large_loop = std::thread(large_loop, s);
+  for (int l = 0; l < s->cfg.large_streams; ++l) s->large_loops.emplace_back(large_loop, s, l);
   *out = s;
   return SPKADD_OK;
 }
@@ -465,19 +474,19 @@ spkadd_status spkadd_server_destroy(spkadd_server_t s) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->cv_work.notify_all();
   }
-  s->large_loop.join();
+  for (std::thread& th : s->large_loops) th.join();
   for (Lane& ln : s->lanes) {
     (void)hipStreamSynchronize(ln.stream);
     for (auto& b : ln.batch) spkadd_batch_destroy(b);
   }
-  (void)hipStreamSynchronize(s->large_stream);
+  for (hipStream_t ls : s->large_streams) (void)hipStreamSynchronize(ls);
   for (auto& kv : s->tickets)
     if (kv.second.out) (void)hipFreeAsync(kv.second.out, s->free_stream);
   for (auto& kv : s->pool)
     for (char* p : kv.second) (void)hipFreeAsync(p, s->free_stream);
   (void)hipStreamSynchronize(s->free_stream);
   for (Lane& ln : s->lanes) (void)hipStreamDestroy(ln.stream);
-  (void)hipStreamDestroy(s->large_stream);
+  for (hipStream_t ls : s->large_streams) (void)hipStreamDestroy(ls);
   (void)hipStreamDestroy(s->free_stream);
   delete s;
   return SPKADD_OK;

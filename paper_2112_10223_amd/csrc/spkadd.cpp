@@ -86,7 +86,7 @@ class WorkspaceCache {
       for (size_t t = 0; t < lst.size(); ++t) {
         CachedBlock b = lst[t];
         bool ok = b.stream == stream;
-        if (!ok && b.done) ok = hipEventQuery(b.done) == hipSuccess;
+        if (!ok && b.done) ok = block_idle(b);
         if (ok) {
           if (b.done) (void)hipEventDestroy(b.done);
           lst.erase(lst.begin() + (long)t);
@@ -125,7 +125,7 @@ class WorkspaceCache {
       auto& lst = kv.second;
       for (size_t t = 0; t < lst.size();) {
         CachedBlock b = lst[t];
-        if (!b.done || hipEventQuery(b.done) == hipSuccess) {
+        if (!b.done || block_idle(b)) {
           if (b.done) (void)hipEventDestroy(b.done);
           (void)hipFree(b.ptr);
           lst.erase(lst.begin() + (long)t);
@@ -137,6 +137,20 @@ class WorkspaceCache {
   }
 
  private:
+  // Whether the work queued before a block's release has completed.  A query leaves
+  // its status in the thread's last-error state (also "not ready"), which is cleared
+  // here so that later launch checks see only their own errors.  An event the runtime
+  // will not query (one recorded while a graph capture was in progress on another
+  // thread) is judged by its stream instead.
+  static bool block_idle(const CachedBlock& b) {
+    hipError_t e = hipEventQuery(b.done);
+    (void)hipGetLastError();
+    if (e == hipSuccess) return true;
+    if (e == hipErrorNotReady) return false;
+    e = hipStreamQuery(b.stream);
+    (void)hipGetLastError();
+    return e == hipSuccess;
+  }
   std::mutex mu_;
   std::map<std::pair<int, size_t>, std::vector<CachedBlock>> free_;
 };
@@ -1058,6 +1072,7 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
                           const int32_t* const* rowidx, spkadd_dtype dtype, const spkadd_opts* opts,
                           hipStream_t stream) {
   g_last_error.clear();
+  (void)hipGetLastError();  // a stale status of the caller's earlier HIP calls
   if (!out) return set_error(SPKADD_ERR_INVALID, "out is NULL");
   *out = nullptr;
   auto* p = new (std::nothrow) spkadd_plan_s();
@@ -1075,6 +1090,7 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
 
 spkadd_status spkadd_symbolic(spkadd_plan_t p, int32_t* colptr_c, int64_t* nnz_c, hipStream_t stream) {
   g_last_error.clear();
+  (void)hipGetLastError();  // a stale status of the caller's earlier HIP calls
   if (!p || !colptr_c || !nnz_c) return set_error(SPKADD_ERR_INVALID, "NULL argument");
   if (p->failed) return set_error(SPKADD_ERR_HIP, "plan failed earlier");
   p->last_stream = stream;
@@ -1120,6 +1136,7 @@ spkadd_status spkadd_symbolic(spkadd_plan_t p, int32_t* colptr_c, int64_t* nnz_c
 spkadd_status spkadd_numeric(spkadd_plan_t p, const void* const* values, int32_t* rowidx_c, void* values_c,
                              hipStream_t stream) {
   g_last_error.clear();
+  (void)hipGetLastError();  // a stale status of the caller's earlier HIP calls
   if (!p) return set_error(SPKADD_ERR_INVALID, "plan is NULL");
   if (p->failed) return set_error(SPKADD_ERR_HIP, "plan failed earlier");
   if (!p->sym_done) return set_error(SPKADD_ERR_STATE, "spkadd_symbolic has not run on this plan");
@@ -1234,6 +1251,7 @@ spkadd_status sum_in_region(void* region, size_t region_bytes, int32_t m, int32_
                             spkadd_dtype dtype, const spkadd_opts* opts, int32_t* colptr_c, int32_t* rowidx_c,
                             void* values_c, int64_t cap_c, int64_t* nnz_c, hipStream_t stream) {
   g_last_error.clear();
+  (void)hipGetLastError();  // a stale status of the caller's earlier HIP calls
   if (!nnz_c || !colptr_c || !values) return set_error(SPKADD_ERR_INVALID, "NULL argument");
   *nnz_c = -1;
   if (cap_c < 0) return set_error(SPKADD_ERR_INVALID, "cap_c must be >= 0");
