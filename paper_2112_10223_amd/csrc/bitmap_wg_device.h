@@ -189,8 +189,8 @@ __device__ __forceinline__ void bitmap_wg_unit(const KArgs& a, unsigned char* sm
   int* outr = a.out_r + o0;
   V* outv = (V*)a.out_v + o0;
   for (int e = tid; e < c; e += NT) {
-    outr[e] = br[e];
-    outv[e] = bv[e];
+    gstore_nt<int>((long long)(outr + e), br[e]);
+    gstore_nt<V>((long long)(outv + e), bv[e]);
   }
 }
 

@@ -156,6 +156,14 @@ __device__ __forceinline__ void gstore(long long addr, T v) {
   *(__attribute__((address_space(1))) T*)addr = v;
 }
 
+// A store that is not read again by this kernel (the output of a numeric pass): the
+// nontemporal hint keeps the written lines from displacing input lines that a
+// neighbouring column is about to read from the L2.
+template <typename T>
+__device__ __forceinline__ void gstore_nt(long long addr, T v) {
+  __builtin_nontemporal_store(v, (__attribute__((address_space(1))) T*)addr);
+}
+
 // A wave-uniform 64-bit value moved into scalar registers (lane 0's copy).  The
 // builtin returns int: each half goes through unsigned so it is not sign-extended.
 __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long x) {

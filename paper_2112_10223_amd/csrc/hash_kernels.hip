@@ -134,8 +134,8 @@ __global__ __launch_bounds__(256) void k_num_wave(KArgs a, const int* __restrict
   int* outr = a.out_r + o0;
   V* outv = (V*)a.out_v + o0;
   for (int e = lane; e < c; e += 64) {
-    outr[e] = ks[e];
-    outv[e] = vs[e];
+    gstore_nt<int>((long long)(outr + e), ks[e]);
+    gstore_nt<V>((long long)(outv + e), vs[e]);
   }
 }
 
@@ -318,8 +318,8 @@ __global__ __launch_bounds__(NT) void k_hash_wg(KArgs a, const int* __restrict__
   int* outr = a.out_r + o0;
   V* outv = (V*)a.out_v + o0;
   for (int e = tid; e < c; e += NT) {
-    outr[e] = ks[e];
-    outv[e] = vs[e];
+    gstore_nt<int>((long long)(outr + e), ks[e]);
+    gstore_nt<V>((long long)(outv + e), vs[e]);
   }
 }
 

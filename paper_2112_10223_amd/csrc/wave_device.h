@@ -152,8 +152,8 @@ __device__ __forceinline__ void write_column(const KArgs& a, int o0, int c, cons
 #pragma unroll
   for (int t = 0; t < E; ++t) {
     const unsigned q = (unsigned)min(64 * t + lane, last);
-    gstore<int>((long long)(sob + (unsigned long long)(q * 4u)), rr[t]);
-    gstore<V>((long long)(sov + (unsigned long long)(q * (unsigned)sizeof(V))), vv[t]);
+    gstore_nt<int>((long long)(sob + (unsigned long long)(q * 4u)), rr[t]);
+    gstore_nt<V>((long long)(sov + (unsigned long long)(q * (unsigned)sizeof(V))), vv[t]);
   }
 }
 
@@ -589,6 +589,18 @@ __host__ __device__ inline void pipe_layout(int E, bool numeric, int vbytes, int
   int off = bm_nq > 0 ? bm_bytes : hash_bytes;
   off = (off + 15) & ~15;
   a.off_hist = ((ts_max + 64) * 4 + (ts_max + 64) * vbytes + 15) & ~15;  // used by the hash layout only
+  const int meta_bytes = ((8 * E + 15) & ~15) + (numeric ? 64 * 16 : 64 * 8);
+  if (numeric && bm_nq > 0 && meta_bytes <= bm_nq * 256) {
+    // The start mask and the segment table of the next unit are read (its loads
+    // issued) before this unit writes its prefix words, and written again only after
+    // the unit's ranks are read: they share the prefix region.
+    a.off_mark = a.off_pre;
+    a.off_P = a.off_adj = a.off_pre + ((8 * E + 15) & ~15);
+    a.off_adjv = a.off_adj;
+    a.slice_bytes = off;
+    a.ts_max = ts_max;
+    return;
+  }
   a.off_mark = off;
   off += 8 * E;
   off = (off + 15) & ~15;
