@@ -152,11 +152,18 @@ void spkadd_opts_default(spkadd_opts* opts);
  *   rowidx : HOST array of k DEVICE pointers, each int32[colptr_i[n]].
  *   dtype  : value type of the later spkadd_numeric calls.
  *   opts   : NULL for defaults.
- *   stream : HIP stream for all device work.  This call waits once for the bin
- *            counts, and a few more times when some columns need row windows.
+ *   stream : HIP stream for all device work.  The call normally returns without
+ *            waiting for the device: the bin counts are copied back asynchronously,
+ *            and spkadd_symbolic (or spkadd_get_stats) waits for them after it has
+ *            launched the symbolic pass of the columns binned for one wavefront,
+ *            which reads the bins on the device.  The row windows are then built in
+ *            that call.  The plan waits here instead (once for the bin counts, a
+ *            few more times for row windows) when SPKADD_FLAG_VALIDATE is set, when
+ *            some rowidx pointer is NULL, and when k > 64 or load_factor_num is not
+ *            0.5 (the wave bins then take one launch each).
  * Errors: INVALID (null pointers, k < 1, negative sizes, bad option values, or
- * malformed inputs when SPKADD_FLAG_VALIDATE is set), OVERFLOW (some u_j above
- * INT32_MAX), OOM, HIP.
+ * malformed inputs when SPKADD_FLAG_VALIDATE is set), OOM, HIP; OVERFLOW (some u_j
+ * above INT32_MAX) here when the plan waits, else from spkadd_symbolic.
  */
 spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, const int32_t* const* colptr,
                           const int32_t* const* rowidx, spkadd_dtype dtype, const spkadd_opts* opts,
@@ -168,8 +175,12 @@ spkadd_status spkadd_plan(spkadd_plan_t* out, int32_t m, int32_t n, int32_t k, c
  * exclusive scan.
  *   colptr_c : DEVICE int32[n+1], written with colptr(B).  It must stay valid until
  *              spkadd_numeric has finished, which reads it.
- *   nnz_c    : HOST int64 receiving nnz(B).  This call waits on the stream.
- * Errors: INVALID (null arguments), OVERFLOW (nnz(B) > INT32_MAX), HIP.
+ *   nnz_c    : HOST int64 receiving nnz(B).  This call waits on the stream.  When
+ *              the plan's stream differs, the first call orders itself after the
+ *              plan's device work.
+ * Errors: INVALID (null arguments), OVERFLOW (nnz(B) > INT32_MAX, or some u_j above
+ * INT32_MAX when spkadd_plan did not wait), UNSUPPORTED (row windows that need more
+ * LDS than the device has, when spkadd_plan did not wait), HIP.
  * It may be called again; every call recomputes the counts.
  */
 spkadd_status spkadd_symbolic(spkadd_plan_t plan, int32_t* colptr_c, int64_t* nnz_c, hipStream_t stream);
@@ -233,8 +244,8 @@ spkadd_status spkadd_free(spkadd_plan_t plan);
  * valid until the next call from the same thread. */
 const char* spkadd_last_error(void);
 
-/* Per-plan statistics, filled after spkadd_plan; the nnz_out and pass fields after
- * spkadd_symbolic. */
+/* Per-plan statistics, filled after spkadd_plan (a plan that has not waited for its
+ * bin counts waits here); nnz_out after spkadd_symbolic. */
 typedef struct spkadd_stats {
   int64_t nnz_in;        /* sum_i nnz(A_i) */
   int64_t nnz_out;       /* nnz(B), -1 before spkadd_symbolic */

@@ -17,7 +17,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 LIB_PATH = os.path.join(HERE, "libspkadd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["plan_kernels.hip", "hash_kernels.hip", "wave_kernels.hip", "batch_kernels.hip", "batch_fused.hip", "bitmap_wg.hip", "unsorted_kernels.hip", "ordered.hip", "baselines.hip", "spkadd.cpp", "noalloc.cpp", "batch.cpp", "server.cpp",
+SOURCES = ["plan_kernels.hip", "hash_kernels.hip", "wave_kernels.hip", "batch_kernels.hip", "batch_fused.hip", "bitmap_wg.hip", "unsorted_kernels.hip", "ordered.hip", "wave_fused.hip", "baselines.hip", "spkadd.cpp", "noalloc.cpp", "batch.cpp", "server.cpp",
            "autotune.cpp"]
 
 COMMON_FLAGS = [

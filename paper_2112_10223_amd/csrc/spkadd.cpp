@@ -17,6 +17,7 @@
 #include "internal.h"
 #include "ordered.h"
 #include "region.h"
+#include "wave_fused.h"
 
 using namespace spk;
 
@@ -302,6 +303,9 @@ struct spkadd_plan_s {
   int32_t* colptr_c = nullptr;
   int64_t nnz_c = -1;
   bool sym_done = false;
+  // the plan's summary copy is queued but not yet waited for (spkadd_symbolic waits)
+  bool pending = false;
+  hipStream_t plan_stream = nullptr;
   // trace
   std::vector<TraceRec> trace;
   // region mode (the no-allocation entry point): every workspace array is carved
@@ -842,7 +846,35 @@ hipError_t launch_bin(spkadd_plan_s* p, int b, bool numeric, KArgs& a_in, hipStr
   return launch_hash(b, numeric, f64, a, list, cnt, s);
 }
 
+// The fused symbolic launch of the wave bins (wave_fused.hip): each bin's accumulator
+// and table size, the largest LDS slice of any wave bin, and the grid (resident
+// blocks).  False when some wave bin does not take the pipelined kernel or the
+// slices do not fit.
+bool wave_sym_fused_setup(const spkadd_plan_s* p, KArgs& a, WaveBinTable& t, unsigned& blocks) {
+  int slice = 0;
+  for (int wi = 0; wi < NWAVE_BINS; ++wi) {
+    const int b = BIN_W1 + wi;
+    KArgs x{};
+    if (!layout_bin(p, b, false, x)) return false;
+    t.bm_nq[wi] = x.bm_nq;
+    t.ts[wi] = p->ts_sym[b];
+    if (x.slice_bytes > slice) slice = x.slice_bytes;
+  }
+  int bpc = max_lds_bytes() / (slice * PIPE_WAVES_PER_BLOCK);
+  if (bpc > 16 / PIPE_WAVES_PER_BLOCK) bpc = 16 / PIPE_WAVES_PER_BLOCK;  // four wavefronts per SIMD
+  if (bpc < 1) return false;
+  a.slice_bytes = slice;
+  blocks = (unsigned)(p->n_cu * bpc);
+  return true;
+}
+
+spkadd_status plan_finish(spkadd_plan_s* p, hipStream_t stream);
+
 void release_all(spkadd_plan_s* p) {
+  if (p->pending) {  // the summary copy into the pinned slot may still be in flight
+    if (wait_summary(p) != SPKADD_OK) (void)hipGetLastError();
+    p->pending = false;
+  }
   hipStream_t s = p->last_stream;
   for (auto& a : p->allocs) WorkspaceCache::get().release(a.p, a.bytes, p->device, s);
   p->allocs.clear();
@@ -1021,6 +1053,31 @@ spkadd_status plan_build(spkadd_plan_s* p, int32_t m, int32_t n, int32_t k, cons
     launch_bin_scan(nblk, o.wave_merge == 0, p->d_hist, p->d_binoff, p->d_sum, stream);
   }
   if ((e = hipGetLastError())) return hipfail(e, "plan kernels");
+  // Deferred wait: the column lists are built, then the summary copy is queued, and
+  // spkadd_symbolic waits for it once the symbolic pass of the wave bins (which needs
+  // no bin count on the host) is running.  The plan waits here when it validates its
+  // inputs (the validation errors are the plan's), when an input has no row array,
+  // in region mode (pageable summaries) and when the wave bins do not take the
+  // pipelined kernels.
+  bool defer = !p->region_mode && !(o.flags & SPKADD_FLAG_VALIDATE) && wave_pipe_ok(k, p->alpha_num_q);
+  for (int i = 0; i < k && defer; ++i) defer = rowidx[i] != nullptr;
+  if (defer) {
+    KArgs fa{};
+    WaveBinTable ft{};
+    unsigned fb = 0;
+    defer = wave_sym_fused_setup(p, fa, ft, fb);
+  }
+  if (defer) {
+    {
+      TraceScope t(p, "bin_scatter", stream);
+      launch_bin_scatter(p->pp, p->d_bin, p->d_hist, p->d_binoff, p->d_list, stream);
+    }
+    if ((e = hipGetLastError())) return hipfail(e, "plan kernels");
+    if ((st = copy_summary(p, stream))) return fail(st);  // (its event also covers the column lists)
+    p->pending = true;
+    p->plan_stream = stream;
+    return SPKADD_OK;
+  }
   // the host needs the bin counts; the column lists are built while it waits
   if ((st = copy_summary(p, stream))) return fail(st);
   {
@@ -1028,6 +1085,20 @@ spkadd_status plan_build(spkadd_plan_s* p, int32_t m, int32_t n, int32_t k, cons
     launch_bin_scatter(p->pp, p->d_bin, p->d_hist, p->d_binoff, p->d_list, stream);
   }
   if ((e = hipGetLastError())) return hipfail(e, "plan kernels");
+  return plan_finish(p, stream);
+}
+
+// The part of the planning step after the bin counts are on the host: bin offsets,
+// LDS checks and the row windows.
+spkadd_status plan_finish(spkadd_plan_s* p, hipStream_t stream) {
+  p->pending = false;
+  auto fail = [](spkadd_status st) { return st; };
+  auto hipfail = [&](hipError_t e, const char* what) {
+    (void)hipGetLastError();
+    return fail(set_error(SPKADD_ERR_HIP, "%s: %s", what, hipGetErrorString(e)));
+  };
+  hipError_t e;
+  spkadd_status st;
   if ((st = wait_summary(p))) return fail(st);
   if ((st = check_device_err(p))) return fail(st);
   int acc = 0;
@@ -1096,9 +1167,38 @@ spkadd_status spkadd_symbolic(spkadd_plan_t p, int32_t* colptr_c, int64_t* nnz_c
   p->last_stream = stream;
   KArgs a = base_args(p);
   a.alpha_q = p->alpha_sym_q;
+  bool wave_done = false;
+  if (p->pending) {
+    // the wave bins first, from the device's bin lists; then the plan's wait
+    if (stream != p->plan_stream && p->ev_sum && hipStreamWaitEvent(stream, p->ev_sum, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      p->failed = true;
+      return set_error(SPKADD_ERR_HIP, "stream wait on the plan failed");
+    }
+    KArgs fa = a;
+    WaveBinTable ft{};
+    unsigned fb = 0;
+    if (wave_sym_fused_setup(p, fa, ft, fb)) {
+      TraceScope t(p, "sym_wave", stream);
+      hipError_t e = launch_wave_sym_fused(fa, ft, p->d_list, p->d_binoff, fb, stream);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p->failed = true;
+        return set_error(SPKADD_ERR_HIP, "symbolic launch (sym_wave): %s", hipGetErrorString(e));
+      }
+      wave_done = true;
+    }
+    spkadd_status st = plan_finish(p, stream);
+    if (st) {
+      p->failed = true;
+      return st;
+    }
+    a = base_args(p);  // (the window arrays exist now)
+    a.alpha_q = p->alpha_sym_q;
+  }
   for (int b = BIN_W1; b < NBINS; ++b) {
     const int cnt = b == BIN_WIN ? p->n_windows : p->bin_count[b];
-    if (cnt == 0) continue;
+    if (cnt == 0 || (wave_done && is_wave(b))) continue;
     TraceScope t(p, hash_kernel_name(b, false), stream);
     hipError_t e = launch_bin(p, b, false, a, stream);
     if (e != hipSuccess) {
@@ -1203,6 +1303,13 @@ spkadd_status spkadd_free(spkadd_plan_t p) {
 
 spkadd_status spkadd_get_stats(spkadd_plan_t p, spkadd_stats* out) {
   if (!p || !out) return set_error(SPKADD_ERR_INVALID, "NULL argument");
+  if (p->pending) {
+    const spkadd_status st = plan_finish(p, p->last_stream);
+    if (st) {
+      p->failed = true;
+      return st;
+    }
+  }
   spkadd_stats s{};
   s.nnz_in = (int64_t)p->h_sum->nnz_in;
   s.nnz_out = p->sym_done ? p->nnz_c : -1;

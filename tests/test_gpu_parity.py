@@ -397,6 +397,68 @@ def test_state_and_validation_errors():
     binding.spkadd_plan(b.m, b.n, cps, ris, binding.SPKADD_F32, _opts(flags=binding.SPKADD_FLAG_VALIDATE)).free()
 
 
+def _hstack(batches):
+    """The columns of several batches (same m and k) side by side."""
+    k, m, n = batches[0].k, batches[0].m, sum(x.n for x in batches)
+    colptr = np.zeros((k, n + 1), dtype=np.int32)
+    rows, vals = [], []
+    for i in range(k):
+        off = pos = 0
+        for x in batches:
+            colptr[i, pos:pos + x.n] = x.colptr[i][:-1] + off
+            pos += x.n
+            off += int(x.colptr[i][-1])
+        colptr[i, n] = off
+        rows.append(np.concatenate([x.rowidx[i] for x in batches]))
+        vals.append(np.concatenate([x.vals[i] for x in batches]))
+    return workloads.CSCBatch(m, n, colptr, rows, vals)
+
+
+def test_plan_without_waiting():
+    """spkadd_plan returns before the device has binned the columns; the symbolic pass
+    takes the wave bins in one launch and then waits for the plan.  A plan freed or
+    queried before its symbolic pass, and a symbolic pass on another stream than the
+    plan, still give the oracle's result."""
+    import torch
+    from paper_2112_10223_amd import binding
+    from tests.gpu_util import to_device
+    note("plan_without_waiting")
+    # every wave bin, workgroup columns and windowed columns in one input
+    b = _hstack([workloads.er(6000, 40, 24, d, seed=s, values="int32f") for s, d in
+                 enumerate([0.5, 2.0, 3.5, 6.0, 9.0, 12.0, 17.0, 22.0, 30.0, 40.0, 80.0, 200.0])])
+    ref = oracle.spkadd(b)
+    cps, ris, vas = to_device(b)
+    opts = _opts(window_cap=2048)  # workgroup columns up to 2048 entries, windows above
+    # freed before its symbolic pass
+    binding.spkadd_plan(b.m, b.n, cps, ris, binding.SPKADD_F32, opts).free()
+    # queried before its symbolic pass
+    plan = binding.spkadd_plan(b.m, b.n, cps, ris, binding.SPKADD_F32, opts)
+    st = binding.spkadd_get_stats(plan)
+    assert st["nnz_out"] == -1 and st["n_wave_cols"] > 0 and st["n_wg_cols"] > 0 and st["n_window_cols"] > 0
+    cp = torch.empty(b.n + 1, dtype=torch.int32, device="cuda:0")
+    nnz = binding.spkadd_symbolic(plan, cp)
+    r = torch.empty(nnz, dtype=torch.int32, device="cuda:0")
+    v = torch.empty(nnz, dtype=torch.float32, device="cuda:0")
+    binding.spkadd_numeric(plan, vas, r, v)
+    torch.cuda.synchronize()
+    assert_matches(b, (cp.cpu().numpy().astype(np.int64), r.cpu().numpy(), v.cpu().numpy()), ref, exact_values=True)
+    plan.free()
+    # plan on one stream, the passes on another
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(s1):
+        plan = binding.spkadd_plan(b.m, b.n, cps, ris, binding.SPKADD_F32, opts, stream=s1)
+    cp2 = torch.empty(b.n + 1, dtype=torch.int32, device="cuda:0")
+    with torch.cuda.stream(s2):
+        nnz2 = binding.spkadd_symbolic(plan, cp2, stream=s2)
+        r2 = torch.empty(nnz2, dtype=torch.int32, device="cuda:0")
+        v2 = torch.empty(nnz2, dtype=torch.float32, device="cuda:0")
+        binding.spkadd_numeric(plan, vas, r2, v2, stream=s2)
+    s2.synchronize()
+    assert_matches(b, (cp2.cpu().numpy().astype(np.int64), r2.cpu().numpy(), v2.cpu().numpy()), ref,
+                   exact_values=True)
+    plan.free()
+
+
 def test_trace_records_kernels():
     from paper_2112_10223_amd import binding
     import torch
