@@ -851,6 +851,9 @@ def main() -> int:
                     help="distinct requests of the served workload (drawn on the device)")
     ap.add_argument("--no-sub", action="store_true",
                     help="time only --workload (not also the fp64, tall-skinny and R-MAT workloads)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched runs of the served pool (runs of 40), e.g. for a kernel trace of the "
+                         "runs without the serving threads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the SpKAdd path here is single-GPU.",
@@ -865,6 +868,11 @@ def main() -> int:
     if not os.path.exists(binding.LIB_PATH):
         import __graft_entry__
         __graft_entry__.build()
+    if args.batched_only:
+        pool = RequestPool(args.served_pool)
+        rec = batched_throughput(pool, PlainRunner(pool), binding.make_opts(), 40, reps=1)
+        print(json.dumps({"batched_only": rec, "pool_requests": args.served_pool}))
+        return 0
 
     desc, make = WORKLOADS[args.workload]
     batch = make()

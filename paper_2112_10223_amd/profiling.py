@@ -14,6 +14,7 @@ Usage (host side, after the GPU runs):
   python -m paper_2112_10223_amd.profiling trace STATS_CSV OUT.txt "COMMAND"
   python -m paper_2112_10223_amd.profiling traffic KERNEL_SUBSTR FETCH_CSV WRITE_CSV \\
       COPY_FETCH_CSV COPY_WRITE_CSV COPY_BYTES ALG_BYTES SOURCE_SHA OUT.md "COMMANDS"
+  python -m paper_2112_10223_amd.profiling timeline KERNEL_TRACE_CSV OUT.txt "COMMAND"
 """
 from __future__ import annotations
 
@@ -96,6 +97,69 @@ def write_traffic_summary(kernel_substr: str, fetch_csv: str, write_csv: str, co
     return rec
 
 
+def run_timeline(trace_csv: str, start_substr: str = "k_batch_init", member_prefixes=("spk::k_batch", "__amd_rocclr")):
+    """Device timeline of batched runs from `--kernel-trace` output: a run starts at a
+    dispatch whose name contains start_substr and takes the following dispatches whose
+    names start with one of member_prefixes.  Per run: span (first start to last end),
+    busy (sum of the dispatch durations) and the gaps between them."""
+    rows = []
+    with open(trace_csv, newline="") as f:
+        for row in csv.DictReader(f):
+            name = _col(row, "Kernel_Name", "Kernel-Name", "KernelName")
+            rows.append((int(_col(row, "Start_Timestamp")), int(_col(row, "End_Timestamp")),
+                         name[5:] if name.startswith("void ") else name))
+    rows.sort()
+    runs, cur = [], None
+    for s, e, name in rows:
+        if start_substr in name:
+            if cur:
+                runs.append(cur)
+            cur = [(s, e, name)]
+        elif cur is not None and name.startswith(member_prefixes):
+            cur.append((s, e, name))
+        elif cur is not None:
+            runs.append(cur)
+            cur = None
+    if cur:
+        runs.append(cur)
+    out = []
+    for r in runs:
+        span = r[-1][1] - r[0][0]
+        busy = sum(e - s for s, e, _ in r)
+        out.append({"dispatches": len(r), "span_us": span / 1e3, "busy_us": busy / 1e3, "gaps_us": (span - busy) / 1e3,
+                    "kernels": [(n, (e - s) / 1e3) for s, e, n in r]})
+    return out
+
+
+def write_timeline_summary(trace_csv: str, out: str, command: str) -> dict:
+    runs = run_timeline(trace_csv)
+    if not runs:
+        raise ValueError(f"no batched run in {trace_csv}")
+    span = sorted(r["span_us"] for r in runs)
+    busy = sorted(r["busy_us"] for r in runs)
+    gaps = sorted(r["gaps_us"] for r in runs)
+
+    def pct(v, q):
+        return v[min(len(v) - 1, int(round(q / 100 * (len(v) - 1))))]
+
+    rec = {"runs": len(runs), "dispatches_per_run_median": int(pct(sorted(r["dispatches"] for r in runs), 50)),
+           "span_us_p50": round(pct(span, 50), 1), "span_us_p90": round(pct(span, 90), 1),
+           "busy_us_p50": round(pct(busy, 50), 1), "gaps_us_p50": round(pct(gaps, 50), 1),
+           "gaps_us_p90": round(pct(gaps, 90), 1),
+           "busy_share_all_runs": round(sum(busy) / max(sum(span), 1e-9), 4)}
+    big = max(runs, key=lambda r: r["span_us"])
+    with open(out, "w") as f:
+        f.write(f"# device timeline of batched runs (rocprofv3 kernel trace)\n# command: {command}\n")
+        f.write("# a run: k_batch_init and the batched-run dispatches after it; span = first start to last end,\n"
+                "# busy = sum of dispatch durations, gaps = span - busy (launch gaps inside the replayed graph)\n")
+        for key, val in rec.items():
+            f.write(f"{key}: {val}\n")
+        f.write(f"\nlongest run ({big['span_us']:.1f} us span, {big['busy_us']:.1f} us busy):\n")
+        for name, us in big["kernels"]:
+            f.write(f"  {name.replace('void ', '')[:70]:<70} {us:>9.1f} us\n")
+    return rec
+
+
 def _largest(path: str) -> tuple[float, str]:
     best, name = 0.0, ""
     with open(path, newline="") as f:
@@ -119,6 +183,8 @@ def read_traffic_summary(path: str) -> dict:
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         write_trace_summary(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "timeline":
+        print(write_timeline_summary(sys.argv[2], sys.argv[3], sys.argv[4]))
     elif sys.argv[1] == "traffic":
         k, fc, wc, cfc, cwc, cb, ab, sha, out, cmds = sys.argv[2:12]
         print(write_traffic_summary(k, fc, wc, cfc, cwc, int(cb), int(ab), sha, out, cmds))
