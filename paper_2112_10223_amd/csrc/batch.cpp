@@ -158,8 +158,9 @@ int enqueue_wg(spkadd_batch_s* b, bool numeric, hipStream_t s) {
   a.err = b->args.err;
   a.dummy = b->args.dummy;
   a.alpha_q = 512;
-  // every workgroup-slot column has at most BATCH_WG_U entries, all in registers
-  lds_layout_bitmap_wg(numeric, f64 ? 8 : 4, 64, BATCH_WG_SPAN, BATCH_WG_U, BATCH_WG_U, true, 2, a);
+  // every workgroup-slot column has at most wg_max (<= BATCH_WG_U) entries, all in
+  // registers: the staging area holds wg_max of them
+  lds_layout_bitmap_wg(numeric, f64 ? 8 : 4, 64, BATCH_WG_SPAN, b->args.wg_max, BATCH_WG_U, true, 2, a);
   // resident workgroups per CU: LDS-bound, at most 32 waves
   const int max_blocks = 32 / (b->wg_threads / 64);
   int bpc = max_lds_bytes() / a.slice_bytes;

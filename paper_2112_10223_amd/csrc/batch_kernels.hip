@@ -60,23 +60,26 @@ __global__ __launch_bounds__(256) void k_batch_init(BatchArgs b) {
   if (t == 0) *b.err = 0;
 }
 
-// Block c handles columns [c * b.chunk, (c + 1) * b.chunk) in 256-column steps.
-__global__ __launch_bounds__(256) void k_batch_bounds(BatchArgs b) {
+// Block c handles columns [c * b.chunk, (c + 1) * b.chunk) in steps of blockDim.x
+// columns (up to 1024: a column's inputs are read in dependent rounds, so the columns
+// of a block are taken side by side rather than one step after another).
+__global__ __launch_bounds__(1024) void k_batch_bounds(BatchArgs b) {
   __shared__ int cnt[BSLOTS];
-  __shared__ int wh[4][BSLOTS];
+  __shared__ int wh[16][BSLOTS];
   __shared__ int cbase[BATCH_LDS_REQS];
   const int lane = lane_id(), w = threadIdx.x >> 6;
+  const int nt = (int)blockDim.x, nw = nt >> 6;
   const int nreq = b.hdr->nreq, total = b.hdr->total_cols;
   if (threadIdx.x < BSLOTS) cnt[threadIdx.x] = 0;
   if (nreq <= BATCH_LDS_REQS)
-    for (int i = threadIdx.x; i < nreq; i += 256) cbase[i] = b.reqs[i].col_base;
+    for (int i = threadIdx.x; i < nreq; i += nt) cbase[i] = b.reqs[i].col_base;
   __syncthreads();
   const int c0 = blockIdx.x * b.chunk;
-  for (int step = 0; step < b.chunk; step += 256) {
+  for (int step = 0; step < b.chunk; step += nt) {
     const int g = c0 + step + threadIdx.x;
-    int slot = -1;
-    if (g < total) {
-      const int r = request_of(b.reqs, cbase, nreq, g);
+    int slot = -1, r = -1;
+    if (g < total && step + (int)threadIdx.x < b.chunk) {
+      r = request_of(b.reqs, cbase, nreq, g);
       const BatchReq& q = b.reqs[r];
       const int j = g - q.col_base;
       // 16 inputs per round; the next round's colptr pointers are loaded together with
@@ -111,8 +114,7 @@ __global__ __launch_bounds__(256) void k_batch_bounds(BatchArgs b) {
       } else if (u > b.wave_max && u <= b.wg_max && q.m <= BATCH_WG_SPAN) {
         slot = BSLOT_WG;
       } else if (u > b.wave_max) {
-        slot = BSLOT_LARGE;
-        atomicOr(&b.status[r], REQ_TOO_LARGE);
+        slot = BSLOT_LARGE;  // (the request's outcome is set below, once per wavefront and request)
       } else {
         const int wi = batch_wave_index((int)u);
         const int E = wave_bin_E(BIN_W1 + wi);
@@ -122,13 +124,26 @@ __global__ __launch_bounds__(256) void k_batch_bounds(BatchArgs b) {
       }
       b.slot[g] = (unsigned char)slot;
     }
+    {
+      // a request with many long columns would otherwise send one atomic per column
+      // to the same word: the first lane of each run of one request's long columns
+      // in the wavefront sets it
+      const bool large = slot == BSLOT_LARGE;
+      const uint64_t lm = ballot(large);
+      const int rprev = __shfl_up(r, 1, 64);
+      const bool prev_large = lane > 0 && ((lm >> (lane - 1)) & 1ull);
+      if (large && !(prev_large && rprev == r)) atomicOr(&b.status[r], REQ_TOO_LARGE);
+    }
     for (int s = 0; s < BSLOTS; ++s) {
       const uint64_t mk = ballot(slot == s);
       if (lane == 0) wh[w][s] = __popcll(mk);
     }
     __syncthreads();
-    if (threadIdx.x < BSLOTS) cnt[threadIdx.x] += wh[0][threadIdx.x] + wh[1][threadIdx.x] + wh[2][threadIdx.x] +
-                                                   wh[3][threadIdx.x];
+    if (threadIdx.x < BSLOTS) {
+      int add = 0;
+      for (int v = 0; v < nw; ++v) add += wh[v][threadIdx.x];
+      cnt[threadIdx.x] += add;
+    }
     __syncthreads();
   }
   if (threadIdx.x < BSLOTS) b.hist[blockIdx.x * BSLOTS + threadIdx.x] = cnt[threadIdx.x];
@@ -244,7 +259,7 @@ __global__ __launch_bounds__(BATCH_SCAN_THREADS) void k_batch_scan(BatchArgs b) 
 // ---- host launchers ----
 void launch_batch_plan(const BatchArgs& b, hipStream_t s) {
   k_batch_init<<<(b.max_reqs + 255) / 256 > 4 ? (b.max_reqs + 255) / 256 : 4, 256, 0, s>>>(b);
-  k_batch_bounds<<<b.nblk, 256, 0, s>>>(b);
+  k_batch_bounds<<<b.nblk, b.chunk < 1024 ? b.chunk : 1024, 0, s>>>(b);
   k_batch_slot_scan<<<1, 1024, 0, s>>>(b);
   k_batch_scatter<<<b.nblk, 256, 0, s>>>(b);
 }

@@ -456,42 +456,58 @@ __global__ __launch_bounds__(WSL_THREADS) void k_win_search_lin(PlanParams p, co
 }
 
 // Input count of every window; windows with more than cap_in entries and more than
-// cap_in rows are cut into q equal row ranges (q[w] = 1 otherwise).
+// cap_in rows are cut into q equal row ranges (q[w] = 1 otherwise).  One wavefront
+// per window at a time, lane i reading input i's two boundary positions (coalesced:
+// the k positions of a boundary are contiguous), windows dealt out over the launch's
+// wavefronts.
 __global__ __launch_bounds__(256) void k_win_count(PlanParams p, int n_windows, const int* __restrict__ win_c,
                                                    const int* __restrict__ brow, const int* __restrict__ bpos,
                                                    int* __restrict__ cntin, int* __restrict__ q,
                                                    PlanSummary* __restrict__ sum) {
-  const int w = blockIdx.x * 256 + threadIdx.x;
-  if (w >= n_windows) return;
-  const int b = w + win_c[w];
-  long long cnt = 0;
-  if (bpos) {
-    const int* lo = bpos + (long long)b * p.k;
-    const int* hi = lo + p.k;
-    for (int i = 0; i < p.k; ++i) cnt += max(hi[i] - lo[i], 0);  // (inverted only for an unsorted input)
-  } else {
-    cnt = cntin[w];  // counted by histogram (unsorted input)
+  const int lane = lane_id();
+  const int nwave = (int)gridDim.x * 4;
+  int wmax = 0, nref = 0;  // over this wavefront's windows
+  for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < n_windows; w += nwave) {
+    const int b = w + win_c[w];
+    long long cnt = 0;
+    if (bpos) {
+      const int* lo = bpos + (long long)b * p.k;
+      const int* hi = lo + p.k;
+      long long part = 0;
+      for (int i = lane; i < p.k; i += 64) part += max(hi[i] - lo[i], 0);  // (inverted only for an unsorted input)
+      cnt = wave_sum<long long>(part);
+    } else {
+      cnt = cntin[w];  // counted by histogram (unsorted input)
+    }
+    const int width = brow[b + 1] - brow[b];
+    wmax = max(wmax, width);
+    int pieces = 1;
+    long long qq = 1;
+    if (cnt > p.cap_in && width > p.cap_in) {
+      const double target = (double)p.cap_in * (double)p.win_fill;
+      qq = (long long)ceil((double)cnt / (target > 1.0 ? target : 1.0));
+      if (qq < 2) qq = 2;
+    }
+    if (width > p.win_span) {  // wider than the workgroup bitmap: equal pieces that fit it
+      const long long qw = ((long long)width + p.win_span - 1) / p.win_span;
+      if (qw > qq) qq = qw;
+    }
+    if (qq > 1) {
+      if (qq > width) qq = width;
+      pieces = (int)qq;
+      ++nref;
+    }
+    if (lane == 0) {
+      cntin[w] = cnt > INT_MAX ? INT_MAX : (int)cnt;
+      q[w] = pieces;
+    }
   }
-  const int width = brow[b + 1] - brow[b];
-  atomicMax(&sum->max_span, width);
-  int pieces = 1;
-  long long qq = 1;
-  if (cnt > p.cap_in && width > p.cap_in) {
-    const double target = (double)p.cap_in * (double)p.win_fill;
-    qq = (long long)ceil((double)cnt / (target > 1.0 ? target : 1.0));
-    if (qq < 2) qq = 2;
+  // the widest window and the windows still to refine: one atomic of each per
+  // wavefront (one per window would all go to the same two words)
+  if (lane == 0) {
+    if (wmax > 0) atomicMax(&sum->max_span, wmax);
+    if (nref) atomicAdd(&sum->pad, nref);
   }
-  if (width > p.win_span) {  // wider than the workgroup bitmap: equal pieces that fit it
-    const long long qw = ((long long)width + p.win_span - 1) / p.win_span;
-    if (qw > qq) qq = qw;
-  }
-  if (qq > 1) {
-    if (qq > width) qq = width;
-    pieces = (int)qq;
-    atomicAdd(&sum->pad, 1);  // number of windows still to refine
-  }
-  cntin[w] = cnt > INT_MAX ? INT_MAX : (int)cnt;
-  q[w] = pieces;
 }
 
 // One refinement level: window w becomes q[w] equal row ranges.  newfirst is the
@@ -766,7 +782,9 @@ void launch_win_search(const PlanParams& p, const int* const* d_cp, const int* c
 void launch_win_count(const PlanParams& p, int n_windows, const int* d_win_c, const int* d_brow, const int* d_bpos,
                       int* d_cntin, int* d_q, PlanSummary* d_sum, hipStream_t s) {
   if (n_windows == 0) return;
-  k_win_count<<<grid_for(n_windows, 256), 256, 0, s>>>(p, n_windows, d_win_c, d_brow, d_bpos, d_cntin, d_q, d_sum);
+  // one wavefront per window at a time: about 16 windows per wavefront
+  const int blocks = (int)((n_windows + 63) / 64) > 4096 ? 4096 : (int)((n_windows + 63) / 64);
+  k_win_count<<<blocks > 0 ? blocks : 1, 256, 0, s>>>(p, n_windows, d_win_c, d_brow, d_bpos, d_cntin, d_q, d_sum);
 }
 
 void launch_win_refine_fill(int n_windows, int n_wcols, const int* d_win_c, const int* d_wfirst_old,
