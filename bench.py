@@ -415,12 +415,15 @@ def alone_vs_mix(pool_size: int, picks, rate: float, seed: int, opts=None, serve
                          max_columns=max(sc["max_batch"] * pool.max_n, 1 << 17), max_inputs=sc["max_batch"] * 64,
                          hbm_budget=SERVE_BUDGET, depth=sc["depth"], opts=opts, large_streams=sc["large_streams"])
 
+    side = torch.cuda.Stream()  # (the null stream refuses work while the server's lanes capture)
+
     def digest(res):
-        cp, r, v = srv.outputs(res)
-        w = torch.arange(r.numel(), device=r.device, dtype=torch.int64) % 1021 + 1
-        wc = torch.arange(cp.numel(), device=cp.device, dtype=torch.int64) % 1019 + 1
-        return (int(res["nnz"]), int((cp.to(torch.int64) * wc).sum()), int((r.to(torch.int64) * w).sum()),
-                float((v.to(torch.float64) * w.to(torch.float64)).sum()))
+        with torch.cuda.stream(side):
+            cp, r, v = srv.outputs(res)
+            w = torch.arange(r.numel(), device=r.device, dtype=torch.int64) % 1021 + 1
+            wc = torch.arange(cp.numel(), device=cp.device, dtype=torch.int64) % 1019 + 1
+            return (int(res["nnz"]), int((cp.to(torch.int64) * wc).sum()), int((r.to(torch.int64) * w).sum()),
+                    float((v.to(torch.float64) * w.to(torch.float64)).sum()))
 
     alone = []
     for q in pool.reqs:

@@ -420,8 +420,13 @@ def _hip_runtime():
     if _hip is None:
         import torch  # noqa: F401  (loads the runtime torch was built with)
         _hip = ctypes.CDLL("libamdhip64.so")
-        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
-        _hip.hipMemcpy.restype = ctypes.c_int
+        _hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                        ctypes.c_void_p]
+        _hip.hipMemcpyAsync.restype = ctypes.c_int
+        _hip.hipStreamCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+        _hip.hipStreamCreateWithFlags.restype = ctypes.c_int
+        _hip.hipStreamSynchronize.argtypes = [ctypes.c_void_p]
+        _hip.hipStreamSynchronize.restype = ctypes.c_int
     return _hip
 
 
@@ -472,7 +477,10 @@ class Server:
 
     def outputs(self, res: dict):
         """Copies of a completed ticket's colptr(B), rows and values (torch, device),
-        made with a device-to-device hipMemcpy of the server-owned arrays."""
+        made on torch's current stream, which is synchronised before returning (the
+        ticket's arrays may be reused once it is released).  While the server's threads
+        capture graphs, the legacy (null) stream refuses work: call this under a
+        torch.cuda.stream of its own."""
         import torch
         n, z = res["n"], max(res["nnz"], 0)
         vdt = torch.float64 if self.dtype == SPKADD_F64 else torch.float32
@@ -480,12 +488,17 @@ class Server:
         r = torch.empty(max(z, 1), dtype=torch.int32, device="cuda")[:z]
         v = torch.empty(max(z, 1), dtype=vdt, device="cuda")[:z]
         hip = _hip_runtime()
+        st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
         for dst, src, nbytes in ((cp, res["colptr_c"], 4 * (n + 1)), (r, res["rowidx_c"], 4 * z),
                                  (v, res["values_c"], v.element_size() * z)):
             if nbytes:
-                err = hip.hipMemcpy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src), ctypes.c_size_t(nbytes), 3)
+                err = hip.hipMemcpyAsync(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src), ctypes.c_size_t(nbytes),
+                                         3, st)
                 if err != 0:
-                    raise RuntimeError(f"hipMemcpy failed: {err}")
+                    raise RuntimeError(f"hipMemcpyAsync failed: {err}")
+        err = hip.hipStreamSynchronize(st)
+        if err != 0:
+            raise RuntimeError(f"hipStreamSynchronize failed: {err}")
         return cp, r, v
 
     def info(self) -> dict:

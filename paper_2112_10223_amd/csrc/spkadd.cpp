@@ -1091,7 +1091,6 @@ spkadd_status plan_build(spkadd_plan_s* p, int32_t m, int32_t n, int32_t k, cons
 // The part of the planning step after the bin counts are on the host: bin offsets,
 // LDS checks and the row windows.
 spkadd_status plan_finish(spkadd_plan_s* p, hipStream_t stream) {
-  p->pending = false;
   auto fail = [](spkadd_status st) { return st; };
   auto hipfail = [&](hipError_t e, const char* what) {
     (void)hipGetLastError();
@@ -1099,7 +1098,8 @@ spkadd_status plan_finish(spkadd_plan_s* p, hipStream_t stream) {
   };
   hipError_t e;
   spkadd_status st;
-  if ((st = wait_summary(p))) return fail(st);
+  if ((st = wait_summary(p))) return fail(st);  // (still pending: spkadd_free waits again)
+  p->pending = false;
   if ((st = check_device_err(p))) return fail(st);
   int acc = 0;
   for (int b = 0; b < NBINS; ++b) {

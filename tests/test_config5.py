@@ -53,6 +53,7 @@ def test_served_pool_against_oracle():
     note(f"config5: {len(small)} requests <= 2^24 entries, {len(large)} larger; serving all together")
     srv = binding.Server(binding.SPKADD_F32, n_streams=1, max_batch=8, max_columns=8 * 65536, max_inputs=8 * 64,
                          hbm_budget=64 << 30)
+    side = torch.cuda.Stream()
     tickets = [srv.submit(s.m, cp, ri, va, max(z, 1)) for s, (cp, ri, va, z) in zip(specs, inputs)]
     outputs, lanes = {}, 0
     for i, tk in enumerate(tickets):
@@ -60,8 +61,9 @@ def test_served_pool_against_oracle():
         assert res["status"] == binding.SPKADD_REQ_OK, (i, res)
         lanes += res["path"]
         if i in chosen:
-            cp, r, v = srv.outputs(res)
-            outputs[i] = (cp.cpu().numpy().astype(np.int64), r.cpu().numpy(), v.cpu().numpy())
+            with torch.cuda.stream(side):  # (the null stream refuses work while the lanes capture)
+                cp, r, v = srv.outputs(res)
+                outputs[i] = (cp.cpu().numpy().astype(np.int64), r.cpu().numpy(), v.cpu().numpy())
         srv.release(tk)
     srv.close()
     assert 0 < lanes < pool_size  # both the batched runs and the one-request lane served

@@ -36,19 +36,35 @@ def _mixed(seed, count, values="int32f"):
     return out
 
 
+_side = []
+
+
+def _side_stream():
+    import torch
+    if not _side:
+        _side.append(torch.cuda.Stream())
+    return _side[0]
+
+
 def _submit(srv, b):
-    cps, ris, vas = to_device(b)
+    import torch
+    with torch.cuda.stream(_side_stream()):  # (the null stream refuses work while lanes capture)
+        cps, ris, vas = to_device(b)
+        torch.cuda.current_stream().synchronize()
     cap = max(int(sum(int(b.colptr[i, b.n]) for i in range(b.k))), 1)
     return srv.submit(b.m, cps, ris, vas, cap), (cps, ris, vas)
 
 
 def _collect(srv, tk):
+    import torch
     from paper_2112_10223_amd import binding
     res = srv.wait(tk, timeout=60.0)
     assert res["status"] == binding.SPKADD_REQ_OK, res
-    cp, r, v = srv.outputs(res)
+    with torch.cuda.stream(_side_stream()):  # (the null stream refuses work while lanes capture)
+        cp, r, v = srv.outputs(res)
+        out = (cp.cpu().numpy().astype(np.int64), r.cpu().numpy(), v.cpu().numpy())
     srv.release(tk)
-    return res, (cp.cpu().numpy().astype(np.int64), r.cpu().numpy(), v.cpu().numpy())
+    return res, out
 
 
 @pytest.mark.parametrize("n_streams,depth", [(1, 1), (2, 2)])
