@@ -127,18 +127,28 @@ void launch_bin_scatter(const PlanParams& p, const unsigned char* d_bin, const i
 void launch_win_scan(const PlanParams& p, const int* d_list, const int* d_binoff, const int* d_u, int* d_wfirst,
                      PlanSummary* d_sum, hipStream_t s);
 // First windows of the window columns: row quantiles of each column's longest input
-// (sorted inputs, columns of the binary-search kind), else equal row ranges.
+// (sorted inputs), else equal row ranges.
 void launch_win_fill(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
                      const int* d_u, int n_wcols, const int* d_wfirst, int* d_win_c, int* d_brow, int* d_bcol,
                      hipStream_t s);
+// Every boundary's position in every input: one pass over the window columns' entries
+// in the chunks of launch_uwin_chunks / launch_uwin_chfill into d_bpos_t (input-major,
+// the size of d_bpos), then transposed into d_bpos.
 void launch_win_search(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
-                       const int* d_wfirst, const int* d_u, int n_wcols, int n_bounds, const int* d_bcol,
-                       const int* d_brow, int* d_bpos, hipStream_t s);
+                       const int* d_wfirst, const int* d_brow, const int* d_bcol, int n_bounds, int n_chunks,
+                       const int* d_chfirst, const int* d_chcol, int* d_bpos_t, int* d_bpos, hipStream_t s);
 void launch_win_records(int n_windows, const int* d_wcols, const int* d_win_c, const int* d_brow, int4* d_wrec,
                         hipStream_t s);
+// Work units of the passes over the window columns' entries (the boundary positions
+// of sorted inputs, the window histogram of unsorted ones): chunks of a column's
+// concatenated input segments, or one chunk per column when it has more than
+// WIN_LDS_K inputs (more than the on-chip segment table).
+constexpr int WIN_CHUNK = 4096;       // unsorted inputs' passes
+constexpr int WIN_LOC_CHUNK = 16384;  // boundary positions of sorted inputs
+constexpr int WIN_LDS_K = 1024;
 // Unsorted input (unsorted_kernels.hip): window counts by histogram, the bucket
 // partition of the final windows, and the numeric pass's value gather.
-void launch_uwin_chunks(const PlanParams& p, int n_wcols, const int* d_wcols, const int* d_u, int* d_nch,
+void launch_uwin_chunks(const PlanParams& p, int n_wcols, const int* d_wcols, const int* d_u, int chunk, int* d_nch,
                         hipStream_t s);
 void launch_uwin_chfill(int n_wcols, const int* d_chfirst, int* d_chcol, hipStream_t s);
 void launch_uwin_hist(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int n_chunks,

@@ -252,19 +252,9 @@ __global__ __launch_bounds__(1024) void k_win_scan(PlanParams p, const int* __re
   }
 }
 
-// Whether window column c's boundaries are found by one ordered pass over its rows
-// (k_win_search_lin) rather than a binary search per (boundary, input): when each
-// input holds 1024..8192 rows of the column on average (shorter: a wavefront mostly
-// waits on the loads that start each input; longer: a block's sequential pass over
-// its inputs outlasts the searches).
-__device__ __forceinline__ bool win_search_linear(long long u, int k) {
-  return u >= 1024LL * k && u <= 8192LL * k;
-}
-
 // First windows of each window column.  The paper splits a column's rows equally
 // (Algorithms 7-8: window q covers rows [q m / P, (q + 1) m / P)).  Here, where the
-// inputs are sorted and the column's boundaries are found by binary searches, the
-// boundaries are instead the row quantiles of the column's longest input (the row at
+// inputs are sorted, the boundaries are instead the row quantiles of the column's longest input (the row at
 // position floor(q len / P) of that input's column): for inputs of similar row
 // distributions -- independent R-MAT matrices, whose rows crowd the low indices --
 // every window then holds about u / P entries from the start, where equal row ranges
@@ -287,7 +277,7 @@ __global__ __launch_bounds__(256) void k_win_fill(PlanParams p, const int* const
   const int lane = lane_id(), w = threadIdx.x >> 6;
   // the longest input of the column (lowest index among equals)
   int best_len = -1, best_i = 0;
-  const bool quant = P > 1 && !p.unsorted_in && !win_search_linear(u[j], p.k);
+  const bool quant = P > 1 && !p.unsorted_in;
   if (quant) {
     for (int i = threadIdx.x; i < p.k; i += 256) {
       const int* col = cp[i];
@@ -373,86 +363,219 @@ __device__ __forceinline__ int lower_bound_rows(const int* __restrict__ r, int l
 
 // Position of every boundary row in every input column: bpos[b*k + i] = the first
 // entry of input i's column at or after boundary row b.
+//
+// One pass over the window columns' entries instead of a binary search per (boundary,
+// input), whose probes fetch a cache line of rows for every four bytes they use.
+// Each entry's window is found among the column's boundaries (staged in LDS; searched
+// in global memory when there are more), and boundary q's position in input i is the
+// first entry of i whose window reaches q: entry e writes the boundaries after its
+// predecessor's window (in the same input; none before the input's first entry) up to
+// its own, the input's last entry the boundaries after its window up to the column's
+// last, with the input's end, and an input with no entry in the column writes all of
+// them with its start.  For sorted rows this is the lower bound of every boundary row,
+// each written once; for any rows every position lies in the input's column segment
+// and every boundary is written.  The positions go first into an input-major copy
+// (a column's region holds input i's P + 1 boundaries at i (P + 1) .. i (P + 1) + P),
+// so that one input's boundaries share cache lines, and k_win_bpos_t transposes them
+// into bpos.
+constexpr int WLOC_THREADS = 256;
+constexpr int WLOC_EPT = 8;                         // entries per thread per round
+constexpr int WLOC_ROUND = WLOC_EPT * WLOC_THREADS;  // a chunk is walked in rounds of this many entries
+constexpr int WLOC_LDS = 2048;                      // boundaries of a column staged in LDS
 
-// One binary search per (boundary, input), for the columns that do not take the
-// ordered pass.
-__global__ __launch_bounds__(256) void k_win_search_bs(PlanParams p, const int* const* __restrict__ cp,
-                                                       const int* const* __restrict__ ri,
-                                                       const int* __restrict__ wcols, const int* __restrict__ wfirst,
-                                                       const int* __restrict__ u, int n_bounds,
-                                                       const int* __restrict__ bcol, const int* __restrict__ brow,
-                                                       int* __restrict__ bpos) {
-  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (long long)n_bounds * p.k) return;
-  const int b = (int)(t / p.k), i = (int)(t - (long long)b * p.k);
-  const int c = bcol[b];
-  const int j = wcols[c];
-  if (win_search_linear(u[j], p.k)) return;  // k_win_search_lin's column
-  const int* col = cp[i];
-  const int s = col[j], e = col[j + 1];
-  const int first = wfirst[c] + c, last = wfirst[c + 1] + c;
-  int pos;
-  if (b == first) pos = s;
-  else if (b == last) pos = e;
-  else pos = lower_bound_rows(ri[i], s, e, brow[b]);
-  bpos[t] = pos;
+// The window of row r among boundaries b[lo .. hi]: the largest q in [lo, hi) with
+// b[q] <= r (lo when none is).
+__device__ __forceinline__ int window_of(const int* b, int lo, int hi, int r) {
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (b[mid] <= r) lo = mid;
+    else hi = mid;
+  }
+  return lo;
 }
 
-// The ordered pass: block (c, g) takes inputs 16 g .. 16 g + 15 of window column c, a
-// wavefront one input at a time.  The boundaries are the equal row splits
-// B_q = floor(q m / P), so a row's window is arithmetic: the largest q < P with
-// q m <= (row + 1) P - 1 (a floating-point estimate, corrected by exact integer
-// compares).  Along an input the window index of its rows is kept as a running
-// maximum (so it never decreases, whatever the input), and boundary q's position is
-// the first row whose window reaches q; boundaries after the last row's window are at
-// the segment end.  Every boundary of the input is written once.
-constexpr int WSL_THREADS = 256;
-constexpr int WSL_GROUP = 16;
-__global__ __launch_bounds__(WSL_THREADS) void k_win_search_lin(PlanParams p, const int* const* __restrict__ cp,
-                                                                const int* const* __restrict__ ri,
-                                                                const int* __restrict__ wcols,
-                                                                const int* __restrict__ wfirst,
-                                                                const int* __restrict__ u, int* __restrict__ bpos) {
-  const int groups = (p.k + WSL_GROUP - 1) / WSL_GROUP;
-  const int c = blockIdx.x / groups, g = blockIdx.x - c * groups;
-  const int j = wcols[c];
-  if (!win_search_linear(u[j], p.k)) return;  // k_win_search_bs's column
-  const int first = wfirst[c] + c;
-  const int P = wfirst[c + 1] - wfirst[c];
-  const long long k = p.k, m = p.m;
-  const double inv_m = 1.0 / (double)m;
+// One input's segment [s, e) walked by one wavefront (columns with more inputs than the
+// segment table): the window is kept as a running maximum along the input.
+__device__ __forceinline__ void locate_segment(const int* bnd, int P, const int* __restrict__ r, int s, int e,
+                                               int* out) {
   const int lane = lane_id();
-  const int i1 = min(p.k, (g + 1) * WSL_GROUP);
-  for (int i = g * WSL_GROUP + (threadIdx.x >> 6); i < i1; i += WSL_THREADS / 64) {
-    const int* col = cp[i];
-    const int s = col[j], e = col[j + 1];
-    const int* r = ri[i];
-    int* out = bpos + (long long)first * k + i;  // boundary q at out[q * k]
-    if (lane == 0) {
-      out[0] = s;
-      out[(long long)P * k] = e;
-    }
-    int prevw = 0;  // window of the row before the chunk (0 before the first row)
-    for (int base = s; base < e; base += 64) {
-      const int idx = base + lane;
-      int w = -1;
-      if (idx < e) {
-        const long long lim = ((long long)gload<int>((long long)(r + idx)) + 1) * P - 1;
-        long long q = (long long)((double)lim * inv_m);
-        q = q < 0 ? 0 : q > P - 1 ? P - 1 : q;
-        while (q > 0 && q * m > lim) --q;
-        while (q < P - 1 && (q + 1) * m <= lim) ++q;
-        w = (int)q;
-      }
-      const int wm = max(wave_scan_max(w), prevw);
-      const int up = __shfl_up(wm, 1, 64);
-      const int wprev = lane == 0 ? prevw : up;
-      if (idx < e)
-        for (int q = wprev + 1; q <= wm; ++q) out[(long long)q * k] = idx;
-      prevw = readlane(wm, 63);
-    }
-    for (int q = prevw + 1 + lane; q <= P - 1; q += 64) out[(long long)q * k] = e;
+  int prevw = -1;  // running window before the chunk (-1 before the first row)
+  for (int base = s; base < e; base += 64) {
+    const int idx = base + lane;
+    const int w = idx < e ? window_of(bnd, 0, P, gload<int>((long long)(r + idx))) : -1;
+    const int wm = max(wave_scan_max(w), prevw);
+    const int up = __shfl_up(wm, 1, 64);
+    const int wprev = lane == 0 ? prevw : up;
+    if (idx < e)
+      for (int q = wprev + 1; q <= wm; ++q) out[q] = idx;
+    prevw = readlane(wm, 63);
   }
+  for (int q = prevw + 1 + lane; q <= P; q += 64) out[q] = e;
+}
+
+__device__ __forceinline__ void locate_chunk(const PlanParams& p, const int* const* __restrict__ cp,
+                                             const int* const* __restrict__ ri, int j, const int* bnd, int P,
+                                             int chunk, int nch, const int* segp, const int* segd,
+                                             const long long* sega, int* __restrict__ out) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (p.k > WIN_LDS_K) {
+    // one chunk per column, one input at a time per wavefront
+    for (int i = wv; i < p.k; i += WLOC_THREADS / 64) {
+      const int s = cp[i][j], e = cp[i][j + 1];
+      locate_segment(bnd, P, ri[i], s, e, out + (long long)i * (P + 1));
+    }
+    return;
+  }
+  const int total = segp[p.k];
+  int ktop = 0;  // largest power of two <= k - 1
+  while ((ktop << 1) <= p.k - 1) ktop = ktop ? ktop << 1 : 1;
+  if (p.k == 1) ktop = 0;
+  int wtop = 0;  // largest power of two <= P - 1
+  while ((wtop << 1) <= P - 1) wtop = wtop ? wtop << 1 : 1;
+  if (P <= 1) wtop = 0;
+  // this chunk's entries [e0, e_end); the column's last chunk takes every entry after
+  // the others (more than its share only where the column totals disagree)
+  const bool last = chunk == nch - 1;
+  const long long e0l = (long long)chunk * WIN_LOC_CHUNK;
+  const int e0 = (int)(e0l < total ? e0l : total);
+  const int e_end = last ? total : (int)(e0l + WIN_LOC_CHUNK < total ? e0l + WIN_LOC_CHUNK : total);
+  // inputs with no entry in the column: all boundaries at the segment start (written
+  // by the chunk holding the segment's place, the last chunk for a trailing one)
+  for (int i = tid; i < p.k; i += WLOC_THREADS) {
+    const int at = segp[i];
+    if (at == segp[i + 1] && ((at >= e0 && at < e_end) || (at == total && last)))
+      for (int q = 0; q <= P; ++q) out[(long long)i * (P + 1) + q] = at - segd[i];
+  }
+  // rounds of WLOC_ROUND entries, wavefront wv taking the WLOC_EPT groups of 64
+  // consecutive entries at r0 + 64 (WLOC_EPT wv + t).  The wavefronts need no barrier:
+  // the window before a group's first entry is the previous group's last lane, and
+  // before the wavefront's first group that of the entry before it, loaded and
+  // searched by lane 0.
+  const int wbase = wv * 64 * WLOC_EPT;
+  for (int r0 = e0; r0 < e_end; r0 += WLOC_ROUND) {  // (uniform)
+    const int r1 = e_end - r0 < WLOC_ROUND ? e_end : r0 + WLOC_ROUND;
+    const int g0 = r0 + wbase;  // this wavefront's first entry of the round
+    if (g0 >= r1) continue;  // (uniform per wavefront; no barrier follows)
+    int segv[WLOC_EPT], wv_[WLOC_EPT];
+#pragma unroll
+    for (int t = 0; t < WLOC_EPT; ++t) segv[t] = 0;
+    // the input of each entry: the largest i with segp[i] <= e, all entries' searches
+    // step by step (their LDS reads in flight together)
+    for (int step = ktop; step > 0; step >>= 1)  // (uniform)
+#pragma unroll
+      for (int t = 0; t < WLOC_EPT; ++t) {
+        const int e = min(g0 + 64 * t + lane, r1 - 1);
+        const int c = segv[t] + step;
+        if (c < p.k && segp[c] <= e) segv[t] = c;
+      }
+#pragma unroll
+    for (int t = 0; t < WLOC_EPT; ++t) {
+      const int e = min(g0 + 64 * t + lane, r1 - 1);  // clamped: no guard on the loads
+      wv_[t] = gload<int>(sega[segv[t]] + 4LL * e);
+    }
+    // lane 0: the entry before the wavefront's first, where that continues its input
+    const bool halo = g0 > segp[segv[0]];  // (lane 0's value is the one used)
+    int hrow = 0;
+    if (lane == 0 && halo) hrow = gload<int>(sega[segv[0]] + 4LL * (g0 - 1));
+    // the windows: the largest q < P with bnd[q] <= row, all entries' searches step
+    // by step (lane 0 also searches its halo row)
+    int lo[WLOC_EPT], hlo = 0;
+#pragma unroll
+    for (int t = 0; t < WLOC_EPT; ++t) lo[t] = 0;
+    for (int step = wtop; step > 0; step >>= 1) {  // (uniform)
+#pragma unroll
+      for (int t = 0; t < WLOC_EPT; ++t) {
+        const int c = lo[t] + step;
+        if (c < P && bnd[c] <= wv_[t]) lo[t] = c;
+      }
+      const int c = hlo + step;
+      if (c < P && bnd[c] <= hrow) hlo = c;
+    }
+#pragma unroll
+    for (int t = 0; t < WLOC_EPT; ++t) {
+      const int e = g0 + 64 * t + lane;
+      const int w = lo[t];
+      const int up = __shfl_up(w, 1, 64);
+      const int last_prev = t > 0 ? readlane(lo[t > 0 ? t - 1 : 0], 63) : hlo;
+      if (e >= r1) continue;
+      const int i = segv[t];
+      int prev;
+      if (e == segp[i]) prev = -1;  // the input's first entry
+      else if (lane > 0) prev = up;
+      else prev = last_prev;
+      const int pos = e - segd[i];  // the entry's position in input i
+      int* o = out + (long long)i * (P + 1);
+      for (int q = prev + 1; q <= w; ++q) o[q] = pos;
+      if (e + 1 == segp[i + 1])  // the input's last entry
+        for (int q = w + 1; q <= P; ++q) o[q] = pos + 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(WLOC_THREADS) void k_win_locate(PlanParams p, const int* const* __restrict__ cp,
+                                                             const int* const* __restrict__ ri,
+                                                             const int* __restrict__ wcols,
+                                                             const int* __restrict__ wfirst,
+                                                             const int* __restrict__ brow,
+                                                             const int* __restrict__ chfirst,
+                                                             const int* __restrict__ chcol, int* __restrict__ bpos_t) {
+  // dynamic LDS (win_locate_lds): sega[k] (address of entry e's row: sega[i] + 4 e),
+  // segp[k + 1] (exclusive prefix of the segment lengths), segd[k] (segp[i] minus the
+  // segment start: entry e is position e - segd[i]); no table past WIN_LDS_K inputs
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int kt = p.k <= WIN_LDS_K ? p.k : 0;
+  long long* sega = reinterpret_cast<long long*>(smem);
+  int* segp = reinterpret_cast<int*>(smem + 8 * kt);
+  int* segd = segp + kt + 1;
+  __shared__ int sb[WLOC_LDS];  // the column's boundary rows
+  __shared__ int red[WLOC_THREADS / 64 + 1];
+  const int tid = threadIdx.x;
+  const int c = chcol[blockIdx.x], chunk = blockIdx.x - chfirst[c];
+  const int j = wcols[c];
+  const int first = wfirst[c] + c;
+  const int P = wfirst[c + 1] - wfirst[c];  // windows; boundaries first .. first + P
+  const bool staged = P + 1 <= WLOC_LDS;
+  if (staged)
+    for (int t = tid; t <= P; t += WLOC_THREADS) sb[t] = brow[first + t];
+  if (p.k <= WIN_LDS_K) {
+    int carry = 0;
+    for (int base = 0; base < p.k; base += WLOC_THREADS) {
+      const int i = base + tid;
+      int s = 0, len = 0;
+      const int* r = nullptr;
+      if (i < p.k) {
+        r = ri[i];
+        s = cp[i][j];
+        len = max(cp[i][j + 1] - s, 0);
+      }
+      int chunk_sum = 0;
+      const int ex = block_excl_scan<WLOC_THREADS>(len, red, &chunk_sum);
+      if (i < p.k) {
+        segp[i] = carry + ex;
+        segd[i] = carry + ex - s;
+        sega[i] = (long long)(r + s) - 4LL * (carry + ex);
+      }
+      carry += chunk_sum;
+    }
+    if (tid == 0) segp[p.k] = carry;
+  }
+  __syncthreads();
+  int* out = bpos_t + (long long)first * p.k;  // the column's region, input-major
+  const int nch = chfirst[c + 1] - chfirst[c];
+  if (staged) locate_chunk(p, cp, ri, j, sb, P, chunk, nch, segp, segd, sega, out);
+  else locate_chunk(p, cp, ri, j, brow + first, P, chunk, nch, segp, segd, sega, out);
+}
+
+// bpos[b k + i] from the input-major copy: boundary b = first + q of column c.
+__global__ __launch_bounds__(256) void k_win_bpos_t(long long total, int k, const int* __restrict__ bcol,
+                                                    const int* __restrict__ wfirst, const int* __restrict__ bpos_t,
+                                                    int* __restrict__ bpos) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= total) return;
+  const int b = (int)(t / k), i = (int)(t - (long long)b * k);
+  const int c = bcol[b];
+  const int first = wfirst[c] + c, P = wfirst[c + 1] - wfirst[c];
+  bpos[t] = bpos_t[(long long)first * k + (long long)i * (P + 1) + (b - first)];
 }
 
 // Input count of every window; windows with more than cap_in entries and more than
@@ -768,15 +891,15 @@ void launch_win_fill(const PlanParams& p, const int* const* d_cp, const int* con
 }
 
 void launch_win_search(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
-                       const int* d_wfirst, const int* d_u, int n_wcols, int n_bounds, const int* d_bcol,
-                       const int* d_brow, int* d_bpos, hipStream_t s) {
-  if (n_wcols == 0 || p.k == 0) return;
-  const long long groups = (p.k + WSL_GROUP - 1) / WSL_GROUP;
-  k_win_search_lin<<<(unsigned)(n_wcols * groups), WSL_THREADS, 0, s>>>(p, d_cp, d_ri, d_wcols, d_wfirst, d_u,
-                                                                         d_bpos);
-  const long long work = (long long)n_bounds * p.k;
-  k_win_search_bs<<<grid_for(work, 256), 256, 0, s>>>(p, d_cp, d_ri, d_wcols, d_wfirst, d_u, n_bounds, d_bcol,
-                                                      d_brow, d_bpos);
+                       const int* d_wfirst, const int* d_brow, const int* d_bcol, int n_bounds, int n_chunks,
+                       const int* d_chfirst, const int* d_chcol, int* d_bpos_t, int* d_bpos, hipStream_t s) {
+  if (n_chunks <= 0 || p.k == 0) return;
+  const int kt = p.k <= WIN_LDS_K ? p.k : 0;
+  const size_t lds = (size_t)8 * kt + 4 * (2 * (size_t)kt + 1);
+  k_win_locate<<<(unsigned)n_chunks, WLOC_THREADS, lds, s>>>(p, d_cp, d_ri, d_wcols, d_wfirst, d_brow, d_chfirst,
+                                                            d_chcol, d_bpos_t);
+  const long long total = (long long)n_bounds * p.k;
+  k_win_bpos_t<<<grid_for(total, 256), 256, 0, s>>>(total, p.k, d_bcol, d_wfirst, d_bpos_t, d_bpos);
 }
 
 void launch_win_count(const PlanParams& p, int n_windows, const int* d_win_c, const int* d_brow, const int* d_bpos,

@@ -535,11 +535,32 @@ spkadd_status build_windows(spkadd_plan_s* p, hipStream_t s) {
     TraceScope t(p, "win_fill", s);
     launch_win_fill(p->pp, p->d_cp, p->d_ri, wcols, p->d_u, nwc, p->d_wfirst, p->d_win_c, p->d_brow, p->d_bcol, s);
   }
+  // work units of the pass over the columns' entries: chunks of each column
+  int *d_nch = nullptr, *d_chfirst = nullptr, *d_chcol = nullptr;
+  void* chtmp = nullptr;
+  if ((st = p->alloc(&d_nch, nwc, s))) return st;
+  if ((st = p->alloc(&d_chfirst, (size_t)nwc + 1, s))) return st;
+  if ((st = p->alloc((char**)&chtmp, scan_tmp_bytes(nwc), s))) return st;
+  launch_uwin_chunks(p->pp, nwc, wcols, p->d_u, WIN_LOC_CHUNK, d_nch, s);
+  launch_scan(d_nch, nwc, d_chfirst, &p->d_sum->total, &p->d_sum->err, chtmp, s);
+  if ((st = sync_summary(p, s))) return st;
+  if ((st = check_device_err(p))) return st;
+  const long long nchunks = p->h_sum->total;
+  if (nchunks > INT_MAX / 2) return set_error(SPKADD_ERR_OVERFLOW, "too many window chunks (%lld)", nchunks);
+  int* d_bpos_t = nullptr;
+  if ((st = p->alloc(&d_chcol, (size_t)nchunks, s))) return st;
+  if ((st = p->alloc(&d_bpos_t, ((size_t)W + nwc) * k, s))) return st;
+  launch_uwin_chfill(nwc, d_chfirst, d_chcol, s);
   {
     TraceScope t(p, "win_search", s);
-    launch_win_search(p->pp, p->d_cp, p->d_ri, wcols, p->d_wfirst, p->d_u, nwc, W + nwc, p->d_bcol, p->d_brow,
-                      p->d_bpos, s);
+    launch_win_search(p->pp, p->d_cp, p->d_ri, wcols, p->d_wfirst, p->d_brow, p->d_bcol, W + nwc, (int)nchunks,
+                      d_chfirst, d_chcol, d_bpos_t, p->d_bpos, s);
   }
+  p->release(d_nch, s);
+  p->release(d_chfirst, s);
+  p->release(chtmp, s);
+  p->release(d_chcol, s);
+  p->release(d_bpos_t, s);
   HIP_TRY(hipMemsetAsync(&p->d_sum->pad, 0, 2 * sizeof(int), s));  // pad and max_span
   {
     TraceScope t(p, "win_count", s);
@@ -648,7 +669,7 @@ spkadd_status build_windows_unsorted(spkadd_plan_s* p, hipStream_t s) {
   if ((st = p->alloc(&d_nch, nwc, s))) return st;
   if ((st = p->alloc(&d_chfirst, (size_t)nwc + 1, s))) return st;
   if ((st = p->alloc((char**)&chtmp, scan_tmp_bytes(nwc), s))) return st;
-  launch_uwin_chunks(p->pp, nwc, wcols, p->d_u, d_nch, s);
+  launch_uwin_chunks(p->pp, nwc, wcols, p->d_u, WIN_CHUNK, d_nch, s);
   launch_scan(d_nch, nwc, d_chfirst, &p->d_sum->total, &p->d_sum->err, chtmp, s);
   if ((st = sync_summary(p, s))) return st;
   if ((st = check_device_err(p))) return st;

@@ -13,7 +13,7 @@ namespace spk {
 
 constexpr int UW_THREADS = 256;
 constexpr int UW_LDS_WIN = 4096;  // a column with at most this many windows counts them in LDS
-constexpr int UW_LDS_K = 1024;    // at most this many inputs: one flat pass over the column's entries
+constexpr int UW_LDS_K = WIN_LDS_K;  // at most this many inputs: one flat pass over the column's entries
 
 // The window of `row` among a column's P windows, whose boundary rows are bro[0..P]
 // (bro[0] = 0, bro[P] = m): the largest q < P with bro[q] <= row.
@@ -30,15 +30,15 @@ __device__ __forceinline__ int window_of(const int* __restrict__ bro, int P, int
 // Work units of the window passes: chunks of UW_CHUNK entries of a column's
 // concatenated input segments (one chunk per column when it has more inputs than the
 // on-chip segment table), so that a long column is spread over many workgroups.
-constexpr int UW_CHUNK = 4096;
+constexpr int UW_CHUNK = WIN_CHUNK;
 constexpr int UW_EPT = UW_CHUNK / UW_THREADS;  // entries of a chunk per thread, kept in registers
 
 __global__ __launch_bounds__(256) void k_uwin_nch(PlanParams p, int n_wcols, const int* __restrict__ wcols,
-                                                  const int* __restrict__ u, int* __restrict__ nch) {
+                                                  const int* __restrict__ u, int chunk, int* __restrict__ nch) {
   const int c = blockIdx.x * 256 + threadIdx.x;
   if (c >= n_wcols) return;
   const int uc = u[wcols[c]];
-  nch[c] = p.k <= UW_LDS_K ? max((uc + UW_CHUNK - 1) / UW_CHUNK, 1) : 1;
+  nch[c] = p.k <= UW_LDS_K ? max((int)(((long long)uc + chunk - 1) / chunk), 1) : 1;
 }
 
 __global__ __launch_bounds__(256) void k_uwin_chfill(int n_wcols, const int* __restrict__ chfirst,
@@ -204,10 +204,10 @@ __global__ __launch_bounds__(256) void k_uwin_gather(long long total, const long
   bvals[t] = reinterpret_cast<const V*>(va[(int)(s >> 32)])[(unsigned)s];
 }
 
-void launch_uwin_chunks(const PlanParams& p, int n_wcols, const int* d_wcols, const int* d_u, int* d_nch,
+void launch_uwin_chunks(const PlanParams& p, int n_wcols, const int* d_wcols, const int* d_u, int chunk, int* d_nch,
                         hipStream_t s) {
   if (n_wcols <= 0) return;
-  k_uwin_nch<<<(n_wcols + 255) / 256, 256, 0, s>>>(p, n_wcols, d_wcols, d_u, d_nch);
+  k_uwin_nch<<<(n_wcols + 255) / 256, 256, 0, s>>>(p, n_wcols, d_wcols, d_u, chunk, d_nch);
 }
 
 void launch_uwin_chfill(int n_wcols, const int* d_chfirst, int* d_chcol, hipStream_t s) {
