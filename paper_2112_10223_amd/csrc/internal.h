@@ -106,80 +106,12 @@ struct KArgs {
   int unsorted;           // numeric: 1 = write each column in table order (no sort)
 };
 
-// ---- plan kernels (plan_kernels.hip) ----
-// Device pointers passed by value (kernel arguments) to k_put_ptrs.
-struct PtrChunk {
-  static constexpr int kMax = 128;
-  const void* p[kMax];
-  int count;
-};
+}  // namespace spk
 
-void launch_put_ptrs(const void* const* host_ptrs, int count, const void** d_dst, PlanSummary* d_sum,
-                     void* d_dummy, hipStream_t s);
-void launch_bounds(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int* d_u,
-                   unsigned char* d_bin, int* d_colcnt, int* d_hist, PlanSummary* d_sum, hipStream_t s);
-void launch_validate(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, PlanSummary* d_sum,
-                     hipStream_t s);
-// d_binoff holds 2 NBINS + 1 ints: offsets (NBINS + 1), then the merge map.
-void launch_bin_scan(int nblk, bool merge, int* d_hist, int* d_binoff, PlanSummary* d_sum, hipStream_t s);
-void launch_bin_scatter(const PlanParams& p, const unsigned char* d_bin, const int* d_hist, const int* d_binoff,
-                        int* d_list, hipStream_t s);
-void launch_win_scan(const PlanParams& p, const int* d_list, const int* d_binoff, const int* d_u, int* d_wfirst,
-                     PlanSummary* d_sum, hipStream_t s);
-// First windows of the window columns: row quantiles of each column's longest input
-// (sorted inputs), else equal row ranges.
-void launch_win_fill(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
-                     const int* d_u, int n_wcols, const int* d_wfirst, int* d_win_c, int* d_brow, int* d_bcol,
-                     hipStream_t s);
-// Every boundary's position in every input: one pass over the window columns' entries
-// in the chunks of launch_uwin_chunks / launch_uwin_chfill into d_bpos_t (input-major,
-// the size of d_bpos), then transposed into d_bpos.
-void launch_win_search(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
-                       const int* d_wfirst, const int* d_brow, const int* d_bcol, int n_bounds, int n_chunks,
-                       const int* d_chfirst, const int* d_chcol, int* d_bpos_t, int* d_bpos, hipStream_t s);
-void launch_win_records(int n_windows, const int* d_wcols, const int* d_win_c, const int* d_brow, int4* d_wrec,
-                        hipStream_t s);
-// Work units of the passes over the window columns' entries (the boundary positions
-// of sorted inputs, the window histogram of unsorted ones): chunks of a column's
-// concatenated input segments, or one chunk per column when it has more than
-// WIN_LDS_K inputs (more than the on-chip segment table).
-constexpr int WIN_CHUNK = 4096;       // unsorted inputs' passes
-constexpr int WIN_LOC_CHUNK = 16384;  // boundary positions of sorted inputs
-constexpr int WIN_LDS_K = 1024;
-// Unsorted input (unsorted_kernels.hip): window counts by histogram, the bucket
-// partition of the final windows, and the numeric pass's value gather.
-void launch_uwin_chunks(const PlanParams& p, int n_wcols, const int* d_wcols, const int* d_u, int chunk, int* d_nch,
-                        hipStream_t s);
-void launch_uwin_chfill(int n_wcols, const int* d_chfirst, int* d_chcol, hipStream_t s);
-void launch_uwin_hist(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int n_chunks,
-                      const int* d_wcols, const int* d_wfirst, const int* d_brow, const int* d_chfirst,
-                      const int* d_chcol, int* d_cnt, hipStream_t s);
-void launch_uwin_scatter(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int n_chunks,
-                         const int* d_wcols, const int* d_wfirst, const int* d_brow, const int* d_chfirst,
-                         const int* d_chcol, int* d_gcur, int* d_brows, long long* d_bsrc, hipStream_t s);
-void launch_uwin_bpos(int n_windows, const int* d_win_c, const int* d_wfirst, const int* d_boff, int* d_bpos,
-                      hipStream_t s);
-void launch_uwin_gather(long long total, const long long* d_bsrc, const void* const* d_va, void* d_bvals, bool f64,
-                        hipStream_t s);
-// d_bpos NULL: the counts are already in d_cntin (unsorted input)
-void launch_win_count(const PlanParams& p, int n_windows, const int* d_win_c, const int* d_brow, const int* d_bpos,
-                      int* d_cntin, int* d_q, PlanSummary* d_sum, hipStream_t s);
-void launch_win_refine_fill(int n_windows, int n_wcols, const int* d_win_c, const int* d_wfirst_old,
-                            const int* d_q, const int* d_newfirst, const int* d_brow_old, int* d_win_c_new,
-                            int* d_brow_new, int* d_bcol_new, int* d_bpar, int* d_bpiece, int* d_wfirst_new,
-                            hipStream_t s);
-void launch_win_refine_search(const PlanParams& p, const int* const* d_ri, int n_bounds_new, const int* d_bcol_new,
-                              const int* d_brow_new, const int* d_bpar, const int* d_bpiece, const int* d_q,
-                              const int* d_bpos_old, int* d_bpos_new, hipStream_t s);
-void launch_win_colsum(int n_wcols, const int* d_wcols, const int* d_wfirst, const int* d_win_cnt, int* d_colcnt,
-                       int* d_win_off, hipStream_t s);
+// ---- plan kernels (plan_kernels.hip, unsorted_kernels.hip): host launchers ----
+#include "plan_launch.h"
 
-// Exclusive scan of len int32 counts into out[0..len] (out[len] = total).  The total
-// is also stored as int64 in *d_total; totals above INT32_MAX set ERR_OVERFLOW in
-// *d_err and leave out[] unspecified.  d_tmp needs scan_tmp_bytes(len).
-size_t scan_tmp_bytes(int64_t len);
-void launch_scan(const int* d_in, int64_t len, int* d_out, long long* d_total, int* d_err, void* d_tmp,
-                 hipStream_t s);
+namespace spk {
 
 // ---- hash kernels (hash_kernels.hip) ----
 // LDS bytes needed by one unit of bin b for a phase (per wave for wave bins).

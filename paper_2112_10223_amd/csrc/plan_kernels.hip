@@ -633,13 +633,20 @@ __global__ __launch_bounds__(256) void k_win_count(PlanParams p, int n_windows, 
   }
 }
 
-// One refinement level: window w becomes q[w] equal row ranges.  newfirst is the
-// exclusive scan of q.
+// One refinement level: window w becomes q[w] row ranges.  newfirst is the exclusive
+// scan of q.  With the boundary positions of sorted inputs (bpos_old) a window no wider
+// than the workgroup bitmap is cut at row quantiles of its longest input within the
+// window (as the first windows are, so the pieces hold about equal entries and one
+// level mostly suffices on skewed rows); otherwise, and for a window cut for its
+// width, into equal row ranges.  The cuts are forced strictly increasing inside the
+// window, so any rows give valid windows.
 __global__ __launch_bounds__(256) void k_win_refine_fill(int n_windows, int n_wcols, const int* __restrict__ win_c,
                                                          const int* __restrict__ wfirst_old,
                                                          const int* __restrict__ q,
                                                          const int* __restrict__ newfirst,
-                                                         const int* __restrict__ brow_old,
+                                                         const int* __restrict__ brow_old, int k, int win_span,
+                                                         const int* const* __restrict__ ri,
+                                                         const int* __restrict__ bpos_old,
                                                          int* __restrict__ win_c_new, int* __restrict__ brow_new,
                                                          int* __restrict__ bcol_new, int* __restrict__ bpar,
                                                          int* __restrict__ bpiece, int* __restrict__ wfirst_new) {
@@ -648,9 +655,37 @@ __global__ __launch_bounds__(256) void k_win_refine_fill(int n_windows, int n_wc
     const int c = win_c[w];
     const int pieces = q[w], nw0 = newfirst[w];
     const int rlo = brow_old[w + c], rhi = brow_old[w + c + 1];
+    // the window's longest input (lowest index among equals)
+    int best_len = 0, best_lo = 0, best_i = 0;
+    if (bpos_old && pieces > 1 && rhi - rlo <= win_span) {
+      const int* lo = bpos_old + (long long)(w + c) * k;
+      const int* hi = lo + k;
+      for (int i = 0; i < k; ++i) {
+        const int len = hi[i] - lo[i];
+        if (len > best_len) {
+          best_len = len;
+          best_lo = lo[i];
+          best_i = i;
+        }
+      }
+    }
+    const bool quant = best_len >= pieces;
+    const int* rows = quant ? ri[best_i] : nullptr;
+    int prev = rlo;
     for (int t = 0; t < pieces; ++t) {
       const int nb = nw0 + t + c;
-      brow_new[nb] = rlo + (int)(((long long)t * (long long)(rhi - rlo)) / pieces);
+      int b;
+      if (t == 0) {
+        b = rlo;
+      } else if (quant) {
+        b = rows[best_lo + (int)(((long long)t * best_len) / pieces)];
+        b = max(b, prev + 1);
+        b = min(b, rhi - (pieces - t));
+      } else {
+        b = rlo + (int)(((long long)t * (long long)(rhi - rlo)) / pieces);
+      }
+      prev = b;
+      brow_new[nb] = b;
       bcol_new[nb] = c;
       bpar[nb] = w;
       bpiece[nb] = t;
@@ -910,14 +945,15 @@ void launch_win_count(const PlanParams& p, int n_windows, const int* d_win_c, co
   k_win_count<<<blocks > 0 ? blocks : 1, 256, 0, s>>>(p, n_windows, d_win_c, d_brow, d_bpos, d_cntin, d_q, d_sum);
 }
 
-void launch_win_refine_fill(int n_windows, int n_wcols, const int* d_win_c, const int* d_wfirst_old,
-                            const int* d_q, const int* d_newfirst, const int* d_brow_old, int* d_win_c_new,
-                            int* d_brow_new, int* d_bcol_new, int* d_bpar, int* d_bpiece, int* d_wfirst_new,
-                            hipStream_t s) {
+void launch_win_refine_fill(const PlanParams& p, int n_windows, int n_wcols, const int* d_win_c,
+                            const int* d_wfirst_old, const int* d_q, const int* d_newfirst, const int* d_brow_old,
+                            const int* const* d_ri, const int* d_bpos_old, int* d_win_c_new, int* d_brow_new,
+                            int* d_bcol_new, int* d_bpar, int* d_bpiece, int* d_wfirst_new, hipStream_t s) {
   const int work = (n_windows > n_wcols + 1 ? n_windows : n_wcols + 1);
   k_win_refine_fill<<<grid_for(work, 256), 256, 0, s>>>(n_windows, n_wcols, d_win_c, d_wfirst_old, d_q,
-                                                        d_newfirst, d_brow_old, d_win_c_new, d_brow_new,
-                                                        d_bcol_new, d_bpar, d_bpiece, d_wfirst_new);
+                                                        d_newfirst, d_brow_old, p.k, p.win_span, d_ri, d_bpos_old,
+                                                        d_win_c_new, d_brow_new, d_bcol_new, d_bpar, d_bpiece,
+                                                        d_wfirst_new);
 }
 
 void launch_win_refine_search(const PlanParams& p, const int* const* d_ri, int n_bounds_new, const int* d_bcol_new,

@@ -594,8 +594,8 @@ spkadd_status build_windows(spkadd_plan_s* p, hipStream_t s) {
     if ((st = p->alloc(&q2, W2, s))) return st;
     {
       TraceScope t(p, "win_refine_fill", s);
-      launch_win_refine_fill(W, nwc, p->d_win_c, p->d_wfirst, d_q, d_newfirst, p->d_brow, win_c2, brow2, bcol2,
-                             bpar, bpiece, wfirst2, s);
+      launch_win_refine_fill(p->pp, W, nwc, p->d_win_c, p->d_wfirst, d_q, d_newfirst, p->d_brow, p->d_ri,
+                             p->d_bpos, win_c2, brow2, bcol2, bpar, bpiece, wfirst2, s);
     }
     {
       TraceScope t(p, "win_refine_search", s);
@@ -714,8 +714,8 @@ spkadd_status build_windows_unsorted(spkadd_plan_s* p, hipStream_t s) {
     if ((st = p->alloc(&q2, W2, s))) return st;
     {
       TraceScope t(p, "win_refine_fill", s);
-      launch_win_refine_fill(W, nwc, p->d_win_c, p->d_wfirst, d_q, d_newfirst, p->d_brow, win_c2, brow2, bcol2,
-                             bpar, bpiece, wfirst2, s);
+      launch_win_refine_fill(p->pp, W, nwc, p->d_win_c, p->d_wfirst, d_q, d_newfirst, p->d_brow, p->d_ri,
+                             nullptr, win_c2, brow2, bcol2, bpar, bpiece, wfirst2, s);
     }
     for (void* x : {(void*)p->d_win_c, (void*)p->d_brow, (void*)p->d_bcol, (void*)p->d_cntin, (void*)d_q,
                     (void*)p->d_wfirst, (void*)d_newfirst, tmp, (void*)bpar, (void*)bpiece})
