@@ -41,6 +41,32 @@ __device__ __forceinline__ int sym_insert(int* T, int TS, int r, int mode, int* 
   return 0;
 }
 
+// Value accumulation without LDS floating-point atomics (which are slow on this
+// hardware): a compare-and-swap loop on the value's bit pattern.
+template <typename V>
+__device__ __forceinline__ void lds_add_cas(V* p, V v) {
+  if constexpr (sizeof(V) == 4) {
+    unsigned* q = reinterpret_cast<unsigned*>(p);
+    unsigned old = *q;
+    for (;;) {
+      const unsigned nv = __float_as_uint(__uint_as_float(old) + (float)v);
+      const unsigned prev = atomicCAS(q, old, nv);
+      if (prev == old) break;
+      old = prev;
+    }
+  } else {
+    unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+    unsigned long long old = *q;
+    for (;;) {
+      const unsigned long long nv =
+          (unsigned long long)__double_as_longlong(__longlong_as_double((long long)old) + (double)v);
+      const unsigned long long prev = atomicCAS(q, old, nv);
+      if (prev == old) break;
+      old = prev;
+    }
+  }
+}
+
 // Algorithm 5 (HashAdd) on one entry.
 template <typename V>
 __device__ __forceinline__ void num_insert(int* K, V* Vt, int TS, int r, V v, int mode, int* err) {
@@ -48,7 +74,7 @@ __device__ __forceinline__ void num_insert(int* K, V* Vt, int TS, int r, V v, in
   for (int probe = 0; probe < TS; ++probe) {
     const int old = atomicCAS(&K[s], -1, r);
     if (old == -1 || old == r) {
-      atomicAdd(&Vt[s], v);
+      lds_add_cas<V>(&Vt[s], v);
       return;
     }
     s = (s + 1 == TS) ? 0 : s + 1;

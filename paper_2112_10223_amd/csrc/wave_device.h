@@ -98,31 +98,6 @@ __device__ __forceinline__ int build_unit_meta(const KArgs& a, unsigned char* ba
   return readlane(incl, 63);
 }
 
-// Value accumulation without LDS floating-point atomics (which are slow on this
-// hardware): a compare-and-swap loop on the value's bit pattern.
-template <typename V>
-__device__ __forceinline__ void lds_add_cas(V* p, V v) {
-  if constexpr (sizeof(V) == 4) {
-    unsigned* q = reinterpret_cast<unsigned*>(p);
-    unsigned old = *q;
-    for (;;) {
-      const unsigned nv = __float_as_uint(__uint_as_float(old) + (float)v);
-      const unsigned prev = atomicCAS(q, old, nv);
-      if (prev == old) break;
-      old = prev;
-    }
-  } else {
-    unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
-    unsigned long long old = *q;
-    for (;;) {
-      const unsigned long long nv =
-          (unsigned long long)__double_as_longlong(__longlong_as_double((long long)old) + (double)v);
-      const unsigned long long prev = atomicCAS(q, old, nv);
-      if (prev == old) break;
-      old = prev;
-    }
-  }
-}
 
 // Coalesced write-out of an output column staged in LDS (rows br[0..c), values
 // bv[0..c), rows ascending) at offset o0 of rowidx(B) / values(B).  Lanes past the
