@@ -252,9 +252,19 @@ __global__ __launch_bounds__(1024) void k_win_scan(PlanParams p, const int* __re
   }
 }
 
+__device__ __forceinline__ int lower_bound_rows(const int* __restrict__ r, int lo, int hi, int row) {
+  while (lo < hi) {
+    const int mid = lo + ((hi - lo) >> 1);
+    if (r[mid] < row) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // First windows of each window column.  The paper splits a column's rows equally
-// (Algorithms 7-8: window q covers rows [q m / P, (q + 1) m / P)).  Here, where the
-// inputs are sorted, the boundaries are instead the row quantiles of the column's longest input (the row at
+// (Algorithms 7-8: window q covers rows [q m / P, (q + 1) m / P)), and so do the
+// columns of the ordered pass (win_search_linear).  Elsewhere, where the inputs are
+// sorted, the boundaries are instead the row quantiles of the column's longest input (the row at
 // position floor(q len / P) of that input's column): for inputs of similar row
 // distributions -- independent R-MAT matrices, whose rows crowd the low indices --
 // every window then holds about u / P entries from the start, where equal row ranges
@@ -267,7 +277,8 @@ __global__ __launch_bounds__(256) void k_win_fill(PlanParams p, const int* const
                                                   const int* const* __restrict__ ri, const int* __restrict__ wcols,
                                                   const int* __restrict__ u, int n_wcols,
                                                   const int* __restrict__ wfirst, int* __restrict__ win_c,
-                                                  int* __restrict__ brow, int* __restrict__ bcol) {
+                                                  int* __restrict__ brow, int* __restrict__ bcol,
+                                                  int* __restrict__ wlin) {
   __shared__ int wl[256 / 64], wi[256 / 64];
   __shared__ int carry_s;
   const int c = blockIdx.x;
@@ -307,7 +318,27 @@ __global__ __launch_bounds__(256) void k_win_fill(PlanParams p, const int* const
         best_i = wi[v];
       }
   }
-  const bool use_q = quant && best_len >= P;
+  bool use_q = quant && best_len >= P;
+  if (use_q && win_search_linear(u[j], p.k)) {  // (uniform)
+    // a column of long runs keeps the equal splits (and the ordered pass) where they
+    // hold about equal entries of the longest input: none more than 1.5 times its share
+    // s plus the spread of a uniform sample (4 sqrt(s) + 4)
+    const int* r0 = ri[best_i] + cp[best_i][j];
+    int mx = 0;
+    for (int q = threadIdx.x; q < P; q += 256) {
+      const int a0 = lower_bound_rows(r0, 0, best_len, (int)(((long long)q * p.m) / P));
+      const int a1 = lower_bound_rows(r0, a0, best_len, (int)(((long long)(q + 1) * p.m) / P));
+      mx = max(mx, a1 - a0);
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
+    __syncthreads();
+    if (lane == 0) wl[w] = mx;
+    __syncthreads();
+    for (int v = 0; v < 256 / 64; ++v) mx = max(mx, wl[v]);
+    const double sh = (double)best_len / (double)P;
+    if ((double)mx <= 1.5 * sh + 4.0 * sqrt(sh) + 4.0) use_q = false;
+  }
+  if (wlin && threadIdx.x == 0) wlin[c] = !use_q && !p.unsorted_in && win_search_linear(u[j], p.k) ? 1 : 0;
   const int* rows = use_q ? ri[best_i] + cp[best_i][j] : nullptr;
   if (threadIdx.x == 0) carry_s = INT_MIN;
   __syncthreads();
@@ -352,14 +383,6 @@ __global__ __launch_bounds__(256) void k_win_fill(PlanParams p, const int* const
   }
 }
 
-__device__ __forceinline__ int lower_bound_rows(const int* __restrict__ r, int lo, int hi, int row) {
-  while (lo < hi) {
-    const int mid = lo + ((hi - lo) >> 1);
-    if (r[mid] < row) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
 
 // Position of every boundary row in every input column: bpos[b*k + i] = the first
 // entry of input i's column at or after boundary row b.
@@ -566,16 +589,76 @@ __global__ __launch_bounds__(WLOC_THREADS) void k_win_locate(PlanParams p, const
   else locate_chunk(p, cp, ri, j, brow + first, P, chunk, nch, segp, segd, sega, out);
 }
 
-// bpos[b k + i] from the input-major copy: boundary b = first + q of column c.
+// bpos[b k + i] from the input-major copy: boundary b = first + q of column c (not
+// for the columns of the ordered pass, which writes bpos itself).
 __global__ __launch_bounds__(256) void k_win_bpos_t(long long total, int k, const int* __restrict__ bcol,
-                                                    const int* __restrict__ wfirst, const int* __restrict__ bpos_t,
-                                                    int* __restrict__ bpos) {
+                                                    const int* __restrict__ wfirst, const int* __restrict__ wlin,
+                                                    const int* __restrict__ bpos_t, int* __restrict__ bpos) {
   const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
   if (t >= total) return;
   const int b = (int)(t / k), i = (int)(t - (long long)b * k);
   const int c = bcol[b];
+  if (wlin[c]) return;
   const int first = wfirst[c] + c, P = wfirst[c + 1] - wfirst[c];
   bpos[t] = bpos_t[(long long)first * k + (long long)i * (P + 1) + (b - first)];
+}
+
+// The ordered pass: block (c, g) takes inputs 16 g .. 16 g + 15 of window column c, a
+// wavefront one input at a time.  The boundaries are the equal row splits
+// B_q = floor(q m / P), so a row's window is arithmetic: the largest q < P with
+// q m <= (row + 1) P - 1 (a floating-point estimate, corrected by exact integer
+// compares).  Along an input the window index of its rows is kept as a running
+// maximum (so it never decreases, whatever the input), and boundary q's position is
+// the first row whose window reaches q; boundaries after the last row's window are at
+// the segment end.  Every boundary of the input is written once.
+constexpr int WSL_THREADS = 256;
+constexpr int WSL_GROUP = 16;
+__global__ __launch_bounds__(WSL_THREADS) void k_win_search_lin(PlanParams p, const int* const* __restrict__ cp,
+                                                                const int* const* __restrict__ ri,
+                                                                const int* __restrict__ wcols,
+                                                                const int* __restrict__ wfirst,
+                                                                const int* __restrict__ wlin,
+                                                                int* __restrict__ bpos) {
+  const int groups = (p.k + WSL_GROUP - 1) / WSL_GROUP;
+  const int c = blockIdx.x / groups, g = blockIdx.x - c * groups;
+  if (!wlin[c]) return;  // k_win_locate's column
+  const int j = wcols[c];
+  const int first = wfirst[c] + c;
+  const int P = wfirst[c + 1] - wfirst[c];
+  const long long k = p.k, m = p.m;
+  const double inv_m = 1.0 / (double)m;
+  const int lane = lane_id();
+  const int i1 = min(p.k, (g + 1) * WSL_GROUP);
+  for (int i = g * WSL_GROUP + (threadIdx.x >> 6); i < i1; i += WSL_THREADS / 64) {
+    const int* col = cp[i];
+    const int s = col[j], e = col[j + 1];
+    const int* r = ri[i];
+    int* out = bpos + (long long)first * k + i;  // boundary q at out[q * k]
+    if (lane == 0) {
+      out[0] = s;
+      out[(long long)P * k] = e;
+    }
+    int prevw = 0;  // window of the row before the chunk (0 before the first row)
+    for (int base = s; base < e; base += 64) {
+      const int idx = base + lane;
+      int w = -1;
+      if (idx < e) {
+        const long long lim = ((long long)gload<int>((long long)(r + idx)) + 1) * P - 1;
+        long long q = (long long)((double)lim * inv_m);
+        q = q < 0 ? 0 : q > P - 1 ? P - 1 : q;
+        while (q > 0 && q * m > lim) --q;
+        while (q < P - 1 && (q + 1) * m <= lim) ++q;
+        w = (int)q;
+      }
+      const int wm = max(wave_scan_max(w), prevw);
+      const int up = __shfl_up(wm, 1, 64);
+      const int wprev = lane == 0 ? prevw : up;
+      if (idx < e)
+        for (int q = wprev + 1; q <= wm; ++q) out[(long long)q * k] = idx;
+      prevw = readlane(wm, 63);
+    }
+    for (int q = prevw + 1 + lane; q <= P - 1; q += 64) out[(long long)q * k] = e;
+  }
 }
 
 // Input count of every window; windows with more than cap_in entries and more than
@@ -920,21 +1003,27 @@ void launch_win_scan(const PlanParams& p, const int* d_list, const int* d_binoff
 
 void launch_win_fill(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
                      const int* d_u, int n_wcols, const int* d_wfirst, int* d_win_c, int* d_brow, int* d_bcol,
-                     hipStream_t s) {
+                     int* d_wlin, hipStream_t s) {
   if (n_wcols == 0) return;
-  k_win_fill<<<n_wcols, 256, 0, s>>>(p, d_cp, d_ri, d_wcols, d_u, n_wcols, d_wfirst, d_win_c, d_brow, d_bcol);
+  k_win_fill<<<n_wcols, 256, 0, s>>>(p, d_cp, d_ri, d_wcols, d_u, n_wcols, d_wfirst, d_win_c, d_brow, d_bcol,
+                                     d_wlin);
 }
 
 void launch_win_search(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
-                       const int* d_wfirst, const int* d_brow, const int* d_bcol, int n_bounds, int n_chunks,
-                       const int* d_chfirst, const int* d_chcol, int* d_bpos_t, int* d_bpos, hipStream_t s) {
-  if (n_chunks <= 0 || p.k == 0) return;
+                       const int* d_wfirst, const int* d_wlin, int n_wcols, const int* d_brow, const int* d_bcol,
+                       int n_bounds, int n_chunks, const int* d_chfirst, const int* d_chcol, int* d_bpos_t,
+                       int* d_bpos, hipStream_t s) {
+  if (n_wcols <= 0 || p.k == 0) return;
+  const long long groups = (p.k + WSL_GROUP - 1) / WSL_GROUP;
+  k_win_search_lin<<<(unsigned)(n_wcols * groups), WSL_THREADS, 0, s>>>(p, d_cp, d_ri, d_wcols, d_wfirst, d_wlin,
+                                                                         d_bpos);
+  if (n_chunks <= 0) return;
   const int kt = p.k <= WIN_LDS_K ? p.k : 0;
   const size_t lds = (size_t)8 * kt + 4 * (2 * (size_t)kt + 1);
   k_win_locate<<<(unsigned)n_chunks, WLOC_THREADS, lds, s>>>(p, d_cp, d_ri, d_wcols, d_wfirst, d_brow, d_chfirst,
                                                             d_chcol, d_bpos_t);
   const long long total = (long long)n_bounds * p.k;
-  k_win_bpos_t<<<grid_for(total, 256), 256, 0, s>>>(total, p.k, d_bcol, d_wfirst, d_bpos_t, d_bpos);
+  k_win_bpos_t<<<grid_for(total, 256), 256, 0, s>>>(total, p.k, d_bcol, d_wfirst, d_wlin, d_bpos_t, d_bpos);
 }
 
 void launch_win_count(const PlanParams& p, int n_windows, const int* d_win_c, const int* d_brow, const int* d_bpos,

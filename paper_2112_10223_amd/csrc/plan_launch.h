@@ -29,15 +29,24 @@ void launch_win_scan(const PlanParams& p, const int* d_list, const int* d_binoff
 // (sorted inputs), else equal row ranges.
 void launch_win_fill(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
                      const int* d_u, int n_wcols, const int* d_wfirst, int* d_win_c, int* d_brow, int* d_bcol,
-                     hipStream_t s);
-// Every boundary's position in every input: one pass over the window columns' entries
-// in the chunks of launch_uwin_chunks / launch_uwin_chfill into d_bpos_t (input-major,
-// the size of d_bpos), then transposed into d_bpos.
+                     int* d_wlin, hipStream_t s);
+// Every boundary's position in every input: for the columns of the ordered pass
+// (win_search_linear) one wavefront per input writing d_bpos; for the others one pass
+// over their entries in the chunks of launch_uwin_chunks / launch_uwin_chfill into
+// d_bpos_t (input-major, the size of d_bpos), then transposed into d_bpos.
 void launch_win_search(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, const int* d_wcols,
-                       const int* d_wfirst, const int* d_brow, const int* d_bcol, int n_bounds, int n_chunks,
-                       const int* d_chfirst, const int* d_chcol, int* d_bpos_t, int* d_bpos, hipStream_t s);
+                       const int* d_wfirst, const int* d_wlin, int n_wcols, const int* d_brow, const int* d_bcol,
+                       int n_bounds, int n_chunks, const int* d_chfirst, const int* d_chcol, int* d_bpos_t,
+                       int* d_bpos, hipStream_t s);
 void launch_win_records(int n_windows, const int* d_wcols, const int* d_win_c, const int* d_brow, int4* d_wrec,
                         hipStream_t s);
+// Whether window column c may keep equal row splits found by one ordered pass per
+// input with the window of a row computed arithmetically (k_win_search_lin): when each
+// input holds 1024..8192 rows of the column on average (long sorted runs that one
+// wavefront walks at streaming speed), and k_win_fill finds the equal splits about
+// balanced; other columns take row quantiles and the chunked pass (k_win_locate).
+__host__ __device__ inline bool win_search_linear(long long u, int k) { return u >= 1024LL * k && u <= 8192LL * k; }
+
 // Work units of the passes over the window columns' entries (the boundary positions
 // of sorted inputs, the window histogram of unsorted ones): chunks of a column's
 // concatenated input segments, or one chunk per column when it has more than
@@ -47,8 +56,10 @@ constexpr int WIN_LOC_CHUNK = 16384;  // boundary positions of sorted inputs
 constexpr int WIN_LDS_K = 1024;
 // Unsorted input (unsorted_kernels.hip): window counts by histogram, the bucket
 // partition of the final windows, and the numeric pass's value gather.
-void launch_uwin_chunks(const PlanParams& p, int n_wcols, const int* d_wcols, const int* d_u, int chunk, int* d_nch,
-                        hipStream_t s);
+// d_wlin: no chunk for the columns of the ordered pass (d_wlin[c] set by launch_win_fill),
+// or nullptr
+void launch_uwin_chunks(const PlanParams& p, int n_wcols, const int* d_wcols, const int* d_u, int chunk,
+                        const int* d_wlin, int* d_nch, hipStream_t s);
 void launch_uwin_chfill(int n_wcols, const int* d_chfirst, int* d_chcol, hipStream_t s);
 void launch_uwin_hist(const PlanParams& p, const int* const* d_cp, const int* const* d_ri, int n_chunks,
                       const int* d_wcols, const int* d_wfirst, const int* d_brow, const int* d_chfirst,

@@ -531,9 +531,12 @@ spkadd_status build_windows(spkadd_plan_s* p, hipStream_t s) {
   int* d_q = nullptr;
   if ((st = p->alloc(&d_q, W, s))) return st;
   const int* wcols = p->d_list + p->binoff[BIN_WIN];
+  int* d_wlin = nullptr;  // columns of the ordered pass
+  if ((st = p->alloc(&d_wlin, nwc, s))) return st;
   {
     TraceScope t(p, "win_fill", s);
-    launch_win_fill(p->pp, p->d_cp, p->d_ri, wcols, p->d_u, nwc, p->d_wfirst, p->d_win_c, p->d_brow, p->d_bcol, s);
+    launch_win_fill(p->pp, p->d_cp, p->d_ri, wcols, p->d_u, nwc, p->d_wfirst, p->d_win_c, p->d_brow, p->d_bcol,
+                    d_wlin, s);
   }
   // work units of the pass over the columns' entries: chunks of each column
   int *d_nch = nullptr, *d_chfirst = nullptr, *d_chcol = nullptr;
@@ -541,7 +544,7 @@ spkadd_status build_windows(spkadd_plan_s* p, hipStream_t s) {
   if ((st = p->alloc(&d_nch, nwc, s))) return st;
   if ((st = p->alloc(&d_chfirst, (size_t)nwc + 1, s))) return st;
   if ((st = p->alloc((char**)&chtmp, scan_tmp_bytes(nwc), s))) return st;
-  launch_uwin_chunks(p->pp, nwc, wcols, p->d_u, WIN_LOC_CHUNK, d_nch, s);
+  launch_uwin_chunks(p->pp, nwc, wcols, p->d_u, WIN_LOC_CHUNK, d_wlin, d_nch, s);
   launch_scan(d_nch, nwc, d_chfirst, &p->d_sum->total, &p->d_sum->err, chtmp, s);
   if ((st = sync_summary(p, s))) return st;
   if ((st = check_device_err(p))) return st;
@@ -553,14 +556,15 @@ spkadd_status build_windows(spkadd_plan_s* p, hipStream_t s) {
   launch_uwin_chfill(nwc, d_chfirst, d_chcol, s);
   {
     TraceScope t(p, "win_search", s);
-    launch_win_search(p->pp, p->d_cp, p->d_ri, wcols, p->d_wfirst, p->d_brow, p->d_bcol, W + nwc, (int)nchunks,
-                      d_chfirst, d_chcol, d_bpos_t, p->d_bpos, s);
+    launch_win_search(p->pp, p->d_cp, p->d_ri, wcols, p->d_wfirst, d_wlin, nwc, p->d_brow, p->d_bcol, W + nwc,
+                      (int)nchunks, d_chfirst, d_chcol, d_bpos_t, p->d_bpos, s);
   }
   p->release(d_nch, s);
   p->release(d_chfirst, s);
   p->release(chtmp, s);
   p->release(d_chcol, s);
   p->release(d_bpos_t, s);
+  p->release(d_wlin, s);
   HIP_TRY(hipMemsetAsync(&p->d_sum->pad, 0, 2 * sizeof(int), s));  // pad and max_span
   {
     TraceScope t(p, "win_count", s);
@@ -661,7 +665,8 @@ spkadd_status build_windows_unsorted(spkadd_plan_s* p, hipStream_t s) {
   const int* wcols = p->d_list + p->binoff[BIN_WIN];
   {
     TraceScope t(p, "win_fill", s);
-    launch_win_fill(p->pp, p->d_cp, p->d_ri, wcols, p->d_u, nwc, p->d_wfirst, p->d_win_c, p->d_brow, p->d_bcol, s);
+    launch_win_fill(p->pp, p->d_cp, p->d_ri, wcols, p->d_u, nwc, p->d_wfirst, p->d_win_c, p->d_brow, p->d_bcol,
+                    nullptr, s);
   }
   // work units of the passes over the columns' entries: chunks of each column
   int *d_nch = nullptr, *d_chfirst = nullptr, *d_chcol = nullptr;
@@ -669,7 +674,7 @@ spkadd_status build_windows_unsorted(spkadd_plan_s* p, hipStream_t s) {
   if ((st = p->alloc(&d_nch, nwc, s))) return st;
   if ((st = p->alloc(&d_chfirst, (size_t)nwc + 1, s))) return st;
   if ((st = p->alloc((char**)&chtmp, scan_tmp_bytes(nwc), s))) return st;
-  launch_uwin_chunks(p->pp, nwc, wcols, p->d_u, WIN_CHUNK, d_nch, s);
+  launch_uwin_chunks(p->pp, nwc, wcols, p->d_u, WIN_CHUNK, nullptr, d_nch, s);
   launch_scan(d_nch, nwc, d_chfirst, &p->d_sum->total, &p->d_sum->err, chtmp, s);
   if ((st = sync_summary(p, s))) return st;
   if ((st = check_device_err(p))) return st;

@@ -34,11 +34,14 @@ constexpr int UW_CHUNK = WIN_CHUNK;
 constexpr int UW_EPT = UW_CHUNK / UW_THREADS;  // entries of a chunk per thread, kept in registers
 
 __global__ __launch_bounds__(256) void k_uwin_nch(PlanParams p, int n_wcols, const int* __restrict__ wcols,
-                                                  const int* __restrict__ u, int chunk, int* __restrict__ nch) {
+                                                  const int* __restrict__ u, int chunk,
+                                                  const int* __restrict__ wlin, int* __restrict__ nch) {
   const int c = blockIdx.x * 256 + threadIdx.x;
   if (c >= n_wcols) return;
   const int uc = u[wcols[c]];
-  nch[c] = p.k <= UW_LDS_K ? max((int)(((long long)uc + chunk - 1) / chunk), 1) : 1;
+  nch[c] = wlin && wlin[c] ? 0
+           : p.k <= UW_LDS_K                         ? max((int)(((long long)uc + chunk - 1) / chunk), 1)
+                                                     : 1;
 }
 
 __global__ __launch_bounds__(256) void k_uwin_chfill(int n_wcols, const int* __restrict__ chfirst,
@@ -204,10 +207,10 @@ __global__ __launch_bounds__(256) void k_uwin_gather(long long total, const long
   bvals[t] = reinterpret_cast<const V*>(va[(int)(s >> 32)])[(unsigned)s];
 }
 
-void launch_uwin_chunks(const PlanParams& p, int n_wcols, const int* d_wcols, const int* d_u, int chunk, int* d_nch,
-                        hipStream_t s) {
+void launch_uwin_chunks(const PlanParams& p, int n_wcols, const int* d_wcols, const int* d_u, int chunk,
+                        const int* d_wlin, int* d_nch, hipStream_t s) {
   if (n_wcols <= 0) return;
-  k_uwin_nch<<<(n_wcols + 255) / 256, 256, 0, s>>>(p, n_wcols, d_wcols, d_u, chunk, d_nch);
+  k_uwin_nch<<<(n_wcols + 255) / 256, 256, 0, s>>>(p, n_wcols, d_wcols, d_u, chunk, d_wlin, d_nch);
 }
 
 void launch_uwin_chfill(int n_wcols, const int* d_chfirst, int* d_chcol, hipStream_t s) {
