@@ -333,6 +333,59 @@ def test_same_row_everywhere_and_large_k():
         assert np.array_equal(got[0], np.arange(n + 1)) and (got[1] == 7).all() and (got[2] == k).all()
 
 
+def _csc_from_columns(m, cols_per_input, dtype=np.float32, seed=0):
+    """A CSCBatch from per-input lists of per-column row arrays (sorted, unique), with
+    small integer values (exact in any summation order)."""
+    rng = np.random.default_rng(seed)
+    k, n = len(cols_per_input), len(cols_per_input[0])
+    colptr = np.zeros((k, n + 1), np.int32)
+    rows, vals = [], []
+    for i, cols in enumerate(cols_per_input):
+        colptr[i, 1:] = np.cumsum([len(c) for c in cols])
+        r = np.concatenate(cols).astype(np.int32) if n else np.zeros(0, np.int32)
+        rows.append(r)
+        vals.append(rng.integers(-3, 4, size=r.size).astype(dtype))
+    return workloads.CSCBatch(m, n, colptr, rows, vals)
+
+
+def test_windows_long_runs_and_skewed_runs():
+    """Window columns whose inputs hold long runs of rows: uniform ones keep equal row
+    ranges and the ordered pass per input, skewed ones (rows crowding the low indices)
+    take quantile windows and the chunked pass, and columns of shorter runs the chunked
+    pass too; all in one launch, against the oracle."""
+    note("windows_long_runs_and_skewed_runs")
+    rng = np.random.default_rng(31)
+    m, k = 1 << 20, 4
+    cols = [[] for _ in range(k)]
+    for j in range(24):
+        for i in range(k):
+            if j < 8:  # uniform, 2048 rows per input
+                r = rng.choice(m, size=2048, replace=False)
+            elif j < 16:  # skewed, 2048 rows per input
+                r = np.unique(np.minimum((rng.pareto(1.2, size=4000) * 200).astype(np.int64), m - 1))[:2048]
+            else:  # shorter runs (1 000 rows per input)
+                r = rng.choice(m, size=1000, replace=False)
+            cols[i].append(np.sort(r))
+    b = _csc_from_columns(m, cols, seed=32)
+    got = run_gpu(b, stats=True)
+    assert got[3]["n_window_cols"] == 24 and got[3]["n_windows"] > 24
+    assert_matches(b, got, oracle.spkadd(b), exact_values=True)
+
+
+def test_windows_more_inputs_than_the_segment_table():
+    """Window columns of sorted inputs with more inputs than the boundary pass's segment
+    table (one wavefront per input walks its rows), against the oracle."""
+    note("windows_more_inputs_than_the_segment_table")
+    rng = np.random.default_rng(33)
+    m, k, n = 40000, 1100, 5
+    cols = [[np.sort(rng.choice(m, size=int(rng.integers(0, 7)), replace=False)) for _ in range(n)]
+            for _ in range(k)]
+    b = _csc_from_columns(m, cols, seed=34)
+    got = run_gpu(b, _opts(force_bin=2, window_cap=512), stats=True)
+    assert got[3]["n_windows"] > n
+    assert_matches(b, got, oracle.spkadd(b), exact_values=True)
+
+
 def test_permutation_invariance():
     note("permutation_invariance")
     batch = workloads.er(5000, 500, 12, 25.0, seed=17, values="int32f")
