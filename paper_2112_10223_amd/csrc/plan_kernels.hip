@@ -542,7 +542,7 @@ __global__ __launch_bounds__(WLOC_THREADS) void k_win_locate(PlanParams p, const
                                                              const int* __restrict__ brow,
                                                              const int* __restrict__ chfirst,
                                                              const int* __restrict__ chcol, int* __restrict__ bpos_t) {
-  // dynamic LDS (win_locate_lds): sega[k] (address of entry e's row: sega[i] + 4 e),
+  // dynamic LDS, sized by the launcher: sega[k] (address of entry e's row: sega[i] + 4 e),
   // segp[k + 1] (exclusive prefix of the segment lengths), segd[k] (segp[i] minus the
   // segment start: entry e is position e - segd[i]); no table past WIN_LDS_K inputs
   extern __shared__ __align__(16) unsigned char smem[];
