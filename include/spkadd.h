@@ -225,8 +225,9 @@ spkadd_status spkadd_numeric(spkadd_plan_t plan, const void* const* values, int3
  * Errors: as spkadd_plan / spkadd_symbolic / spkadd_numeric; UNSUPPORTED when the
  * inputs need more workspace than the array holds (about 18 bytes per column plus
  * 24 per input, and, when some column needs row windows, about 8 k + 64 bytes per
- * window and 4 k + 40 per window of each refinement level: with 64 MiB, n up to about 3.5 million columns without
- * windows); INVALID when nnz(B) > cap_c (colptr_c and *nnz_c are then written,
+ * window and 4 k + 40 per window of each refinement level: with 64 MiB, n up to
+ * about 3.5 million columns without windows); INVALID when nnz(B) > cap_c
+ * (colptr_c and *nnz_c are then written,
  * rowidx_c and values_c are not).
  */
 #define SPKADD_NOALLOC_SCRATCH_BYTES (64u << 20)
