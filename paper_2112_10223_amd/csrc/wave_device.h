@@ -133,42 +133,56 @@ __device__ __forceinline__ void write_column(const KArgs& a, int o0, int c, cons
 }
 
 // Algorithms 5 and 6 on E entries per lane of a wavefront-private table, with
-// linear probing.  The entries of one index t are resolved before those of t+1.  A
-// row's probe sequence depends only on the row, so concurrent inserts of the same
-// row meet in the same slot.  NUM: the lane whose claim created the slot stores the
-// value (plain store).  A lane that finds its row already there adds with a
-// compare-and-swap loop.  The table belongs to one wavefront, so program order is
-// the order in LDS, and the store comes first.  SYM counts first claims.
+// linear probing.  Every entry of the wavefront probes at once, one step per round:
+// a lane's E compare-and-swaps are in flight together, and the wavefront waits for
+// its longest probe sequence once rather than once per index t.  A row's probe
+// sequence depends only on the row, so concurrent inserts of the same row meet in
+// the same slot.  NUM: once every row has its slot, the lanes whose claims created
+// slots store their values (plain stores), then the lanes that found their row
+// already there add with a compare-and-swap loop.  SYM counts first claims.
 // Returns this lane's new keys.
 template <int E, bool NUM, typename V>
 __device__ __forceinline__ int insert_batch(int* K, V* Vt, int TS, int mode, int u, const int (&rows)[E],
                                             const V (&vals)[E], int* err) {
   const int lane = lane_id();
+  // per entry: slot in the low 16 bits (TS <= 2048), state above: 0 probing,
+  // 1 claimed the slot, 2 found its row there, 3 no entry
+  constexpr int SH = 16, MASK = (1 << SH) - 1;
+  int code[E];
+#pragma unroll
+  for (int t = 0; t < E; ++t) code[t] = hash_slot(rows[t], TS, mode) | ((lane + 64 * t < u ? 0 : 3) << SH);
+  for (int probe = 0; probe < TS; ++probe) {
+    bool pending = false;
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+      if ((code[t] >> SH) == 0) {
+        const int sl = code[t] & MASK;
+        const int old = atomicCAS(&K[sl], -1, rows[t]);
+        if (old == -1) code[t] = sl | (1 << SH);
+        else if (old == rows[t]) code[t] = sl | (2 << SH);
+        else {
+          code[t] = sl + 1 == TS ? 0 : sl + 1;
+          pending = true;
+        }
+      }
+    }
+    if (ballot(pending) == 0) break;  // (uniform)
+  }
   int newc = 0;
 #pragma unroll
   for (int t = 0; t < E; ++t) {
-    const bool in = lane + 64 * t < u;
-    const int r = rows[t];
-    int s = hash_slot(r, TS, mode);
-    int old = -2;
-    if (in) {
-      int probe = 0;
-      for (; probe < TS; ++probe) {
-        old = atomicCAS(&K[s], -1, r);
-        if (old == -1 || old == r) break;
-        s = s + 1 == TS ? 0 : s + 1;
-      }
-      if (probe == TS) atomicOr(err, ERR_PROBE);
-    }
-    const bool own = in && old == -1;
-    newc += own ? 1 : 0;
-    if (NUM) {
-      // every lane of index t has its slot now: owners store, then the others add
-      if (own) Vt[s] = vals[t];
-      wave_sync();
-      if (in && old == r) lds_add_cas<V>(&Vt[s], vals[t]);
-      wave_sync();
-    }
+    if ((code[t] >> SH) == 0) atomicOr(err, ERR_PROBE);  // a full table: sized wrong
+    newc += (code[t] >> SH) == 1 ? 1 : 0;
+  }
+  if (NUM) {
+#pragma unroll
+    for (int t = 0; t < E; ++t)
+      if ((code[t] >> SH) == 1) Vt[code[t] & MASK] = vals[t];
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < E; ++t)
+      if ((code[t] >> SH) == 2) lds_add_cas<V>(&Vt[code[t] & MASK], vals[t]);
+    wave_sync();
   }
   return newc;
 }
